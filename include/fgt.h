@@ -1,0 +1,134 @@
+/*
+ * fgt.h -- C ABI of the MI355X (gfx950) one-dimensional fast Gauss transform.
+ *
+ * The transform (paper: S. Jiang, "A fast Gauss transform in one dimension
+ * using sum-of-exponentials approximations", arXiv 1909.09825):
+ *
+ *     u_i = sum_{j=1..N} exp(-(x_i - y_j)^2 / (4 delta)) alpha_j,   i = 1..M     (1.1)-(1.2)
+ *
+ * evaluated through a sum-of-exponentials (SOE) approximation of the kernel,
+ *
+ *     exp(-x^2/(4 delta)) ~ S(x) = Re sum_{k=1..n_e} omega_k exp(-tau0_k |x| / sqrt(delta))     (1.3)
+ *
+ * (one node per conjugate pair, weight doubled), by sorting targets and sources
+ * together and running, per mode, the forward recurrence (4.5) and the
+ * backward recurrence (4.6) as parallel affine scans, then accumulating
+ * Re(omega_k (h+ + h-)) at the targets (4.1).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers (hipMalloc'd or equivalent) holding
+ *     contiguous arrays of the plan's element type (double for FGT_F64, float
+ *     for FGT_F32); the caller owns them.  Inputs are only read.
+ *   - Work is enqueued on `stream` and the call returns without synchronising;
+ *     nothing is allocated on the device by fgt_eval.
+ *   - Return value: FGT_OK or a negative-free error code below.  A call that
+ *     returns an error has enqueued nothing.
+ *   - Sizes are element counts.  M + N must be below 2^32.
+ */
+#ifndef FGT_H_
+#define FGT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define FGT_OK 0
+#define FGT_EINVAL 1        /* bad argument: sizes, null pointers, delta, digits, workspace */
+#define FGT_EUNSUPPORTED 2  /* valid request the library does not serve (e.g. FP32 beyond 6 digits) */
+#define FGT_ENONFINITE 3    /* a coordinate was NaN or infinite (reported by fgt_last_device_status) */
+#define FGT_EDEVICE 4       /* a HIP runtime call failed */
+
+/* Element types. */
+#define FGT_F64 0
+#define FGT_F32 1
+
+/* Largest number of modes a plan may hold. */
+#define FGT_MAX_MODES 8
+
+typedef struct fgt_plan_s* fgt_plan_t;
+
+/*
+ * fgt_plan -- choose an SOE table and scale it to delta.
+ *
+ * Picks the smallest shipped table whose measured max error E_n (the
+ * measurement of (3.1): delta = 1, x = 0 and 1e5 log-spaced points on
+ * [1e-5, 1e2], plus a denser check grid) is at most 10^-digits, and scales
+ * the nodes to tau_k = tau0_k / sqrt(delta) (E_n does not depend on delta).
+ *   delta  > 0 and finite.
+ *   digits in [1, fgt_max_digits(dtype)].
+ *   dtype  FGT_F64 or FGT_F32 (FP32 serves at most 6 digits).
+ *   out    receives the plan; the caller releases it with fgt_plan_destroy.
+ * A plan is immutable host data and may be shared by concurrent calls.
+ * Errors: FGT_EINVAL (delta, digits, dtype, null out), FGT_EUNSUPPORTED.
+ */
+int fgt_plan(double delta, int digits, int dtype, fgt_plan_t* out);
+
+/* Largest `digits` fgt_plan accepts for `dtype` (0 for an unknown dtype). */
+int fgt_max_digits(int dtype);
+
+/*
+ * fgt_plan_info -- the plan's table and stated bounds (host pointers; any may be null).
+ *   n_modes          number of modes n_e.
+ *   err_bound        E_n: |S(x) - exp(-x^2/(4 delta))| <= E_n for all x, so
+ *                    |u_SOE - u| <= E_n sum_j |alpha_j| (triangle inequality).
+ *   deriv_err_bound  E'_n: bound on |S'(x) - G'(x)| in units of 1/sqrt(delta).
+ *   tau, omega       2*n_modes doubles each, (re, im) interleaved; tau is the
+ *                    node already divided by sqrt(delta).
+ *   delta            the plan's delta.
+ * Errors: FGT_EINVAL for a null plan.
+ */
+int fgt_plan_info(fgt_plan_t plan, int* n_modes, double* err_bound, double* deriv_err_bound,
+                  double* tau, double* omega, double* delta);
+
+/* Release a plan.  Accepts null. */
+void fgt_plan_destroy(fgt_plan_t plan);
+
+/*
+ * fgt_workspace_size -- bytes of device workspace fgt_eval needs for M targets
+ * and N sources with this plan (0 for a null plan or negative sizes).
+ * The workspace holds the sort keys and permutation (double-buffered), the
+ * radix histograms and look-back state, per-tile scan carries and a status word.
+ */
+size_t fgt_workspace_size(fgt_plan_t plan, int64_t M, int64_t N);
+
+/*
+ * fgt_eval -- u = SOE approximation of (1.1) for targets x[M], sources y[N],
+ * strengths alpha[N]; writes u[M] in the order of x.
+ *   ws/ws_bytes  device workspace of at least fgt_workspace_size(plan, M, N)
+ *                bytes, 256-byte aligned; its contents need not be cleared and
+ *                are clobbered.  One workspace may not be used by two calls at
+ *                once.
+ *   u            may not alias x, y, alpha or ws.
+ * M == 0 enqueues nothing; N == 0 writes zeros.
+ * Non-finite coordinates are detected on the device and reported by
+ * fgt_last_device_status; u is then unspecified.
+ * Errors: FGT_EINVAL (negative sizes, M + N >= 2^32, null pointer with a
+ * non-zero size, workspace too small or misaligned), FGT_EDEVICE.
+ */
+int fgt_eval(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha,
+             int64_t N, void* u, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * fgt_last_device_status -- synchronise `stream`, then read and clear the
+ * status word that the last fgt_eval on workspace `ws` left there.
+ * Returns FGT_OK, FGT_ENONFINITE, or FGT_EINVAL / FGT_EDEVICE.
+ */
+int fgt_last_device_status(void* ws, hipStream_t stream);
+
+/* Human-readable text for a status code (static storage). */
+const char* fgt_strerror(int status);
+
+/* Library version string (static storage). */
+const char* fgt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FGT_H_ */

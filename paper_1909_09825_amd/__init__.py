@@ -1,0 +1,15 @@
+"""One-dimensional fast Gauss transform for AMD MI355X (gfx950).
+
+u_i = sum_j exp(-(x_i - y_j)^2 / (4 delta)) alpha_j through sum-of-exponentials
+approximations of the Gaussian (S. Jiang, arXiv 1909.09825): a device radix
+sort of targets and sources, then forward and backward complex recurrences
+per mode as parallel scans, all in hand-written HIP kernels behind the C ABI
+of include/fgt.h.
+"""
+from ._lib import (FGT_EDEVICE, FGT_EINVAL, FGT_ENONFINITE, FGT_EUNSUPPORTED, FGT_F32, FGT_F64,
+                   FGT_OK, FGTError, LIB_PATH)
+from .api import Plan, eval, last_device_status, max_digits, plan, workspace
+
+__all__ = ["Plan", "plan", "eval", "workspace", "last_device_status", "max_digits", "FGTError",
+           "FGT_OK", "FGT_EINVAL", "FGT_EUNSUPPORTED", "FGT_ENONFINITE", "FGT_EDEVICE",
+           "FGT_F64", "FGT_F32", "LIB_PATH"]

@@ -1,0 +1,205 @@
+// C ABI of the fast Gauss transform: plans, validation, workspace layout and
+// the launch sequence sort -> scan on the caller's stream.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "fgt_internal.h"
+
+namespace fgt {
+
+typedef SoeTable fgt_soe_table_t;
+#include "soe_tables.inc"
+
+namespace {
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Largest digits served per element type: FP64 up to the most accurate
+// shipped table, FP32 up to 6 digits (its rounding unit is 6e-8).
+int max_digits_f64() {
+  int best = 0;
+  for (int i = 0; i < FGT_SOE_NUM_TABLES; ++i) {
+    int d = (int)floor(-log10(kSoeTables[i].err_bound));
+    if (d > best) best = d;
+  }
+  return best;
+}
+
+}  // namespace
+
+Workspace layout(void* base, int64_t P, int esz, int n_modes) {
+  Workspace w;
+  memset(&w, 0, sizeof(w));
+  const int digits = esz == 8 ? 8 : 4;
+  w.sort_tiles = (P + kSortTile - 1) / kSortTile;
+  w.scan_tiles = (P + kScanTile - 1) / kScanTile;
+  if (w.sort_tiles < 1) w.sort_tiles = 1;
+  if (w.scan_tiles < 1) w.scan_tiles = 1;
+  char* b = (char*)base;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = b ? (void*)(b + off) : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  // The region cleared at the start of each call is contiguous: status word
+  // (always at offset 0), histograms, tile counters and the first look-back buffer.
+  w.status = (uint32_t*)take(sizeof(uint32_t) * 64);
+  w.hist = (uint32_t*)take(sizeof(uint32_t) * digits * kRadix);
+  w.tile_ctr = (uint32_t*)take(sizeof(uint32_t) * 8);
+  w.lookback[0] = (uint64_t*)take(sizeof(uint64_t) * (size_t)w.sort_tiles * kRadix);
+  w.zero_bytes = off;
+  w.lookback[1] = (uint64_t*)take(sizeof(uint64_t) * (size_t)w.sort_tiles * kRadix);
+  w.dig_off = (uint32_t*)take(sizeof(uint32_t) * digits * kRadix);
+  w.pass = (PassInfo*)take(sizeof(PassInfo));
+  w.agg = take((size_t)esz * 6 * (size_t)n_modes * (size_t)w.scan_tiles);
+  w.carry = take((size_t)esz * 4 * (size_t)n_modes * (size_t)w.scan_tiles);
+  w.keys[0] = take((size_t)esz * (size_t)P);
+  w.keys[1] = take((size_t)esz * (size_t)P);
+  w.idx[0] = (uint32_t*)take(sizeof(uint32_t) * (size_t)P);
+  w.idx[1] = (uint32_t*)take(sizeof(uint32_t) * (size_t)P);
+  w.total = off;
+  return w;
+}
+
+}  // namespace fgt
+
+struct fgt_plan_s {
+  int dtype;
+  double delta;
+  const fgt::SoeTable* table;
+  fgt::Modes modes;
+};
+
+extern "C" {
+
+const char* fgt_version(void) { return "fgt-mi355x 0.1 (gfx950)"; }
+
+const char* fgt_strerror(int status) {
+  switch (status) {
+    case FGT_OK: return "ok";
+    case FGT_EINVAL: return "invalid argument";
+    case FGT_EUNSUPPORTED: return "unsupported request";
+    case FGT_ENONFINITE: return "non-finite coordinate";
+    case FGT_EDEVICE: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int fgt_max_digits(int dtype) {
+  if (dtype == FGT_F64) return fgt::max_digits_f64();
+  if (dtype == FGT_F32) return 6;
+  return 0;
+}
+
+int fgt_plan(double delta, int digits, int dtype, fgt_plan_t* out) {
+  if (!out) return FGT_EINVAL;
+  *out = nullptr;
+  if (!(delta > 0.0) || !isfinite(delta)) return FGT_EINVAL;
+  if (dtype != FGT_F64 && dtype != FGT_F32) return FGT_EINVAL;
+  if (digits < 1 || digits > fgt::max_digits_f64()) return FGT_EINVAL;
+  if (digits > fgt_max_digits(dtype)) return FGT_EUNSUPPORTED;
+  const double target = pow(10.0, -digits);
+  const fgt::SoeTable* tab = nullptr;
+  for (int i = 0; i < FGT_SOE_NUM_TABLES; ++i) {
+    if (fgt::kSoeTables[i].err_bound <= target &&
+        (!tab || fgt::kSoeTables[i].n_modes < tab->n_modes))
+      tab = &fgt::kSoeTables[i];
+  }
+  if (!tab) return FGT_EUNSUPPORTED;
+  fgt_plan_s* p = new (std::nothrow) fgt_plan_s;
+  if (!p) return FGT_EINVAL;
+  p->dtype = dtype;
+  p->delta = delta;
+  p->table = tab;
+  memset(&p->modes, 0, sizeof(p->modes));
+  p->modes.n = tab->n_modes;
+  const double rs = 1.0 / sqrt(delta);
+  for (int k = 0; k < tab->n_modes; ++k) {
+    p->modes.tau_re[k] = tab->tau0_re[k] * rs;
+    p->modes.tau_im[k] = tab->tau0_im[k] * rs;
+    p->modes.om_re[k] = tab->om_re[k];
+    p->modes.om_im[k] = tab->om_im[k];
+    const double mag = hypot(p->modes.tau_re[k], p->modes.tau_im[k]);
+    p->modes.dz_fast[k] = fgt::kFastR / mag;
+  }
+  *out = p;
+  return FGT_OK;
+}
+
+int fgt_plan_info(fgt_plan_t plan, int* n_modes, double* err_bound, double* deriv_err_bound,
+                  double* tau, double* omega, double* delta) {
+  if (!plan) return FGT_EINVAL;
+  const int n = plan->modes.n;
+  if (n_modes) *n_modes = n;
+  if (err_bound) *err_bound = plan->table->err_bound;
+  if (deriv_err_bound) *deriv_err_bound = plan->table->deriv_err_bound;
+  if (delta) *delta = plan->delta;
+  for (int k = 0; k < n; ++k) {
+    if (tau) {
+      tau[2 * k] = plan->modes.tau_re[k];
+      tau[2 * k + 1] = plan->modes.tau_im[k];
+    }
+    if (omega) {
+      omega[2 * k] = plan->modes.om_re[k];
+      omega[2 * k + 1] = plan->modes.om_im[k];
+    }
+  }
+  return FGT_OK;
+}
+
+void fgt_plan_destroy(fgt_plan_t plan) { delete plan; }
+
+size_t fgt_workspace_size(fgt_plan_t plan, int64_t M, int64_t N) {
+  if (!plan || M < 0 || N < 0) return 0;
+  const int esz = plan->dtype == FGT_F64 ? 8 : 4;
+  return fgt::layout(nullptr, M + N, esz, plan->modes.n).total;
+}
+
+int fgt_eval(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha,
+             int64_t N, void* u, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!plan || M < 0 || N < 0) return FGT_EINVAL;
+  if (M + N >= (int64_t(1) << 32)) return FGT_EINVAL;
+  if (M == 0) return FGT_OK;
+  if (!x || !u) return FGT_EINVAL;
+  const bool f64 = plan->dtype == FGT_F64;
+  if (N == 0) {
+    hipError_t e = f64 ? fgt::fill_zero<double>((double*)u, M, stream)
+                       : fgt::fill_zero<float>((float*)u, M, stream);
+    return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+  }
+  if (!y || !alpha || !ws) return FGT_EINVAL;
+  if (((uintptr_t)ws & 255u) != 0) return FGT_EINVAL;
+  const int esz = f64 ? 8 : 4;
+  const fgt::Workspace w = fgt::layout(ws, M + N, esz, plan->modes.n);
+  if (ws_bytes < w.total) return FGT_EINVAL;
+  hipError_t e;
+  if (f64) {
+    e = fgt::sort_points<double>(w, (const double*)x, M, (const double*)y, N, stream);
+    if (e == hipSuccess)
+      e = fgt::scan_points<double>(w, plan->modes, (const double*)alpha, M, N, (double*)u, stream);
+  } else {
+    e = fgt::sort_points<float>(w, (const float*)x, M, (const float*)y, N, stream);
+    if (e == hipSuccess)
+      e = fgt::scan_points<float>(w, plan->modes, (const float*)alpha, M, N, (float*)u, stream);
+  }
+  return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+}
+
+int fgt_last_device_status(void* ws, hipStream_t stream) {
+  if (!ws) return FGT_EINVAL;
+  // The status word sits at offset 0 of every layout.
+  uint32_t* status = (uint32_t*)ws;
+  uint32_t v = 0;
+  if (hipStreamSynchronize(stream) != hipSuccess) return FGT_EDEVICE;
+  if (hipMemcpy(&v, status, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return FGT_EDEVICE;
+  const uint32_t zero = 0;
+  if (hipMemcpy(status, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
+    return FGT_EDEVICE;
+  if (v & fgt::kStatusNonFinite) return FGT_ENONFINITE;
+  return v ? FGT_EDEVICE : FGT_OK;
+}
+
+}  // extern "C"

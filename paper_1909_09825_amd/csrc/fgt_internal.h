@@ -1,0 +1,124 @@
+// Internal definitions shared by the host API and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/fgt.h"
+
+namespace fgt {
+
+// ---------------------------------------------------------------------------
+// SOE table as shipped (delta = 1) and as a kernel argument (scaled to delta).
+// ---------------------------------------------------------------------------
+struct SoeTable {
+  int n_modes;
+  double tau0_re[FGT_MAX_MODES], tau0_im[FGT_MAX_MODES];
+  double om_re[FGT_MAX_MODES], om_im[FGT_MAX_MODES];
+  double err_bound, deriv_err_bound, sum_abs_omega;
+};
+
+// Passed by value to the scan kernels: tau_k = tau0_k / sqrt(delta), omega_k,
+// and the fast-exponential threshold dz_fast_k = R / |tau_k| (see exp_neg).
+struct Modes {
+  int n;
+  double tau_re[FGT_MAX_MODES], tau_im[FGT_MAX_MODES];
+  double om_re[FGT_MAX_MODES], om_im[FGT_MAX_MODES];
+  double dz_fast[FGT_MAX_MODES];
+};
+
+// ---------------------------------------------------------------------------
+// Tunables.
+// ---------------------------------------------------------------------------
+constexpr int kWave = 64;
+
+// LSD radix sort: 8-bit digits, one-sweep passes with decoupled look-back.
+constexpr int kSortThreads = 256;
+constexpr int kSortWaves = kSortThreads / kWave;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per tile
+constexpr int kRadix = 256;
+constexpr int kHistBlocks = 2048;
+
+// Scan: each thread owns a run of kScanChunk consecutive sorted points.
+constexpr int kScanThreads = 256;
+constexpr int kScanWaves = kScanThreads / kWave;
+constexpr int kScanChunk = 8;
+constexpr int kScanTile = kScanThreads * kScanChunk;   // 2048 points per tile
+constexpr int kCarryThreads = 1024;
+
+// Radius of the Taylor branch of the mode exponential: |tau dz| <= kFastR.
+constexpr double kFastR = 1.0 / 16.0;
+
+template <class T> struct KeyOf;
+template <> struct KeyOf<double> { using type = uint64_t; static constexpr int kDigits = 8; };
+template <> struct KeyOf<float> { using type = uint32_t; static constexpr int kDigits = 4; };
+
+// Order-preserving map from a float to an unsigned key: negative values get
+// all bits flipped, non-negative ones the sign bit set; -0 is mapped to +0 so
+// that equal coordinates get equal keys.
+__device__ __forceinline__ uint64_t to_key(double z) {
+  uint64_t b = (uint64_t)__double_as_longlong(z);
+  if (b == 0x8000000000000000ull) b = 0;
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ uint32_t to_key(float z) {
+  uint32_t b = (uint32_t)__float_as_uint(z);
+  if (b == 0x80000000u) b = 0;
+  return (b >> 31) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ double from_key(uint64_t k) {
+  uint64_t b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ float from_key(uint32_t k) {
+  uint32_t b = (k >> 31) ? (k & 0x7fffffffu) : ~k;
+  return __uint_as_float(b);
+}
+
+// Bits of the device status word.
+constexpr uint32_t kStatusNonFinite = 1u;
+constexpr uint32_t kStatusInternal = 2u;
+
+// ---------------------------------------------------------------------------
+// Workspace layout (all offsets 256-byte aligned).
+// ---------------------------------------------------------------------------
+struct PassInfo {
+  int32_t run[8];     // 1 if radix pass d moves data
+  int32_t src[8];     // 0/1: key buffer it reads, 2: the raw coordinates
+  int32_t final_buf;  // buffer that holds the sorted keys at the end
+  int32_t pad[7];
+};
+
+struct Workspace {
+  void* keys[2];
+  uint32_t* idx[2];
+  uint32_t* status;      // [1] at offset 0, zeroed per call
+  uint32_t* hist;        // [digits][256], zeroed per call
+  uint32_t* tile_ctr;    // [8], zeroed per call
+  uint64_t* lookback[2]; // [sort_tiles][256]; [0] zeroed per call, each pass clears the other
+  uint32_t* dig_off;     // [digits][256]
+  PassInfo* pass;
+  void* agg;             // [scan_tiles][modes][6] scalars: A, F, G (complex)
+  void* carry;           // [scan_tiles][modes][4] scalars: CF, CB (complex)
+  size_t zero_bytes;     // bytes from `status` that the first kernel clears
+  int64_t sort_tiles, scan_tiles;
+  size_t total;
+};
+
+// Layout for P points, element size `esz` (8 or 4), n_modes modes.  With
+// base == nullptr only sizes are computed.
+Workspace layout(void* base, int64_t P, int esz, int n_modes);
+
+// Kernel launch sequences (defined in the .hip files).
+template <class T>
+hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, int64_t N,
+                       hipStream_t s);
+template <class T>
+hipError_t scan_points(const Workspace& w, const Modes& m, const T* alpha, int64_t M, int64_t N,
+                       T* u, hipStream_t s);
+template <class T>
+hipError_t fill_zero(T* u, int64_t n, hipStream_t s);
+
+}  // namespace fgt

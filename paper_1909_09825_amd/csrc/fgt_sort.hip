@@ -1,0 +1,329 @@
+// Stable LSD radix sort of the merged point set [y_1..y_N, x_1..x_M] on gfx950.
+//
+// The paper sorts targets and sources in ascending order before the
+// recurrences (Section 4) and times that step separately (Tables 1-2).  Here
+// both sets are sorted together as order-preserving unsigned keys with a
+// 32-bit payload p (p < N: source p, else target p - N).  Stability places a
+// source before a target with the same coordinate, which realises the
+// "y_j <= x_i belongs to h+" split of (4.4).
+//
+// Kernels, all on the caller's stream:
+//   k_clear       zero histograms, tile counters, status word, look-back[0]
+//   k_histogram   one read of the coordinates: all digit histograms at once,
+//                 plus the non-finite flag
+//   k_plan        per pass: does the digit vary?  where does the pass read
+//                 from and write to?  exclusive digit offsets
+//   k_onesweep    one pass per digit: stable in-tile ranking with wave ballots,
+//                 tile offsets by decoupled look-back (Merrill & Garland),
+//                 scatter staged through LDS so writes are coalesced runs.
+//                 Passes whose digit is constant return at once.
+#include "fgt_internal.h"
+
+namespace fgt {
+namespace {
+
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagPrefix = 2ull << 62;
+constexpr uint64_t kValueMask = (1ull << 62) - 1;
+constexpr int kRaw = 2;
+// A look-back wait longer than this means a predecessor tile never published;
+// the pass then stops waiting and raises kStatusInternal instead of hanging.
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+__global__ void k_clear(uint32_t* __restrict__ p, size_t n_words) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n_words; i += stride) p[i] = 0u;
+}
+
+template <class T>
+__device__ __forceinline__ T load_point(const T* __restrict__ x, const T* __restrict__ y,
+                                        int64_t N, int64_t p) {
+  return p < N ? y[p] : x[p - N];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, const T* __restrict__ y,
+                                                   int64_t N, int64_t P,
+                                                   uint32_t* __restrict__ hist,
+                                                   uint32_t* __restrict__ status) {
+  using K = typename KeyOf<T>::type;
+  constexpr int D = KeyOf<T>::kDigits;
+  __shared__ uint32_t h[D * kRadix];
+  for (int i = threadIdx.x; i < D * kRadix; i += blockDim.x) h[i] = 0u;
+  __syncthreads();
+
+  // Run-length counting per digit: constant high digits (common for
+  // coordinates of one sign and exponent range) cost one LDS atomic per run.
+  uint32_t cur[D], cnt[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) { cur[d] = 0u; cnt[d] = 0u; }
+  bool bad = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += stride) {
+    const T z = load_point(x, y, N, p);
+    bad |= !isfinite(z);
+    const K k = to_key(z);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const uint32_t dig = (uint32_t)(k >> (8 * d)) & 0xffu;
+      if (cnt[d] != 0u && dig != cur[d]) {
+        atomicAdd(&h[d * kRadix + cur[d]], cnt[d]);
+        cnt[d] = 0u;
+      }
+      cur[d] = dig;
+      ++cnt[d];
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (cnt[d]) atomicAdd(&h[d * kRadix + cur[d]], cnt[d]);
+  if (bad) atomicOr(status, kStatusNonFinite);
+  __syncthreads();
+  for (int i = threadIdx.x; i < D * kRadix; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// One block of 256 threads (one per digit value).
+template <class T>
+__global__ __launch_bounds__(256) void k_plan(const uint32_t* __restrict__ hist, int64_t P,
+                                              uint32_t* __restrict__ dig_off,
+                                              PassInfo* __restrict__ pass) {
+  constexpr int D = KeyOf<T>::kDigits;
+  __shared__ uint32_t scan[kRadix];
+  __shared__ int trivial[8];
+  const int b = threadIdx.x;
+  if (b < 8) trivial[b] = 0;
+  __syncthreads();
+  for (int d = 0; d < D; ++d) {
+    const uint32_t c = hist[d * kRadix + b];
+    if ((int64_t)c == P) trivial[d] = 1;
+    scan[b] = c;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over 256 digit counts.
+    for (int o = 1; o < kRadix; o <<= 1) {
+      const uint32_t v = b >= o ? scan[b - o] : 0u;
+      __syncthreads();
+      scan[b] += v;
+      __syncthreads();
+    }
+    dig_off[d * kRadix + b] = scan[b] - c;
+    __syncthreads();
+  }
+  if (b == 0) {
+    int any = 0;
+    for (int d = 0; d < D; ++d) any |= !trivial[d];
+    int runs = 0, last_out = 0;
+    for (int d = 0; d < 8; ++d) {
+      int run = (d < D) && !trivial[d];
+      if (!any && d == D - 1) run = 1;  // all keys equal: one pass materialises them
+      pass->run[d] = run;
+      if (run) {
+        pass->src[d] = runs == 0 ? kRaw : (runs - 1) % 2;
+        last_out = runs % 2;
+        ++runs;
+      } else {
+        pass->src[d] = -1;
+      }
+    }
+    pass->final_buf = last_out;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kSortThreads) void k_onesweep(
+    int d, const T* __restrict__ x, const T* __restrict__ y, int64_t N, int64_t P,
+    void* keys0, void* keys1, uint32_t* idx0, uint32_t* idx1,
+    const uint32_t* __restrict__ dig_off, const PassInfo* __restrict__ pass,
+    uint32_t* __restrict__ tile_ctr, uint64_t* lb_cur, uint64_t* lb_next,
+    uint32_t* __restrict__ status) {
+  using K = typename KeyOf<T>::type;
+  __shared__ uint32_t wcnt[kSortWaves][kRadix];   // per-wave running digit counts, then wave offsets
+  __shared__ uint32_t tstart[kRadix];             // tile-local exclusive digit starts
+  __shared__ uint64_t gbase[kRadix];              // global output position of each digit's run
+  __shared__ K skeys[kSortTile];
+  __shared__ uint32_t sidx[kSortTile];
+  __shared__ int s_tile;
+
+  const int tid = threadIdx.x;
+  const int run = pass->run[d];
+  const int src = pass->src[d];
+  if (!run) {
+    // Nothing moves; still clear the other look-back buffer for the next pass.
+    for (int64_t t = blockIdx.x; t * kSortTile < P; t += gridDim.x)
+      lb_next[(size_t)t * kRadix + tid] = 0ull;
+    return;
+  }
+  if (tid == 0) s_tile = (int)atomicAdd(&tile_ctr[d], 1u);
+  for (int w = 0; w < kSortWaves; ++w) wcnt[w][tid] = 0u;
+  __syncthreads();
+  const int tile = s_tile;
+  lb_next[(size_t)tile * kRadix + tid] = 0ull;
+
+  const K* kin = src == 1 ? (const K*)keys1 : (const K*)keys0;
+  const uint32_t* iin = src == 1 ? idx1 : idx0;
+  K* kout = src == 0 ? (K*)keys1 : (K*)keys0;
+  uint32_t* iout = src == 0 ? idx1 : idx0;
+
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int shift = 8 * d;
+  const int64_t base = (int64_t)tile * kSortTile + (int64_t)wave * (kSortItems * kWave);
+
+  K key[kSortItems];
+  uint32_t id[kSortItems];
+  uint32_t rank[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const int64_t p = base + i * kWave + lane;
+    if (p < P) {
+      if (src == kRaw) {
+        key[i] = to_key(load_point(x, y, N, p));
+        id[i] = (uint32_t)p;
+      } else {
+        key[i] = kin[p];
+        id[i] = iin[p];
+      }
+    } else {
+      key[i] = (K)0;
+      id[i] = 0u;
+    }
+  }
+
+  // Stable ranking inside the wave, items in order (i, lane): lanes with the
+  // same digit are found with 8 ballots; the lowest lane of each group
+  // advances the wave's running count.
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const int64_t p = base + i * kWave + lane;
+    const bool valid = p < P;
+    const uint32_t dig = (uint32_t)(key[i] >> shift) & 0xffu;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (dig >> bit) & 1u;
+      const uint64_t bal = __ballot(on);
+      peers &= on ? bal : ~bal;
+    }
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+    const uint32_t count = (uint32_t)__popcll(peers);
+    const uint32_t before = wcnt[wave][dig];
+    __builtin_amdgcn_wave_barrier();
+    if (valid && below == 0u) wcnt[wave][dig] = before + count;
+    __builtin_amdgcn_wave_barrier();
+    rank[i] = before + below;
+  }
+  __syncthreads();
+
+  // Tile histogram, wave offsets, publish the tile's aggregate.
+  uint32_t tcount = 0u;
+  {
+    uint32_t run_sum = 0u;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) {
+      const uint32_t c = wcnt[w][tid];
+      wcnt[w][tid] = run_sum;
+      run_sum += c;
+    }
+    tcount = run_sum;
+  }
+  __hip_atomic_store(&lb_cur[(size_t)tile * kRadix + tid], kFlagAgg | (uint64_t)tcount,
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+  // Exclusive scan of the tile histogram over digits.
+  tstart[tid] = tcount;
+  __syncthreads();
+  for (int o = 1; o < kRadix; o <<= 1) {
+    const uint32_t v = tid >= o ? tstart[tid - o] : 0u;
+    __syncthreads();
+    tstart[tid] += v;
+    __syncthreads();
+  }
+  const uint32_t tincl = tstart[tid];
+  __syncthreads();
+  tstart[tid] = tincl - tcount;
+
+  // Decoupled look-back over earlier tiles for this digit.
+  uint64_t excl = 0ull;
+  uint32_t spins = 0u;
+  for (int j = tile - 1; j >= 0;) {
+    const uint64_t v = __hip_atomic_load(&lb_cur[(size_t)j * kRadix + tid], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t f = v & ~kValueMask;
+    if (f == 0ull) {
+      if (++spins > kSpinLimit) {
+        atomicOr(status, kStatusInternal);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += v & kValueMask;
+    if (f == kFlagPrefix) break;
+    --j;
+  }
+  __hip_atomic_store(&lb_cur[(size_t)tile * kRadix + tid], kFlagPrefix | (excl + tcount),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  gbase[tid] = (uint64_t)dig_off[d * kRadix + tid] + excl;
+  __syncthreads();
+
+  // Sort the tile by digit in LDS.
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const int64_t p = base + i * kWave + lane;
+    if (p < P) {
+      const uint32_t dig = (uint32_t)(key[i] >> shift) & 0xffu;
+      const uint32_t pos = tstart[dig] + wcnt[wave][dig] + rank[i];
+      if (pos < (uint32_t)kSortTile) {
+        skeys[pos] = key[i];
+        sidx[pos] = id[i];
+      }
+    }
+  }
+  __syncthreads();
+
+  // Write each digit's run to its global position.
+  const int64_t tile_begin = (int64_t)tile * kSortTile;
+  const int nvalid = (int)((P - tile_begin) < kSortTile ? (P - tile_begin) : kSortTile);
+  for (int j = tid; j < nvalid; j += kSortThreads) {
+    const K k = skeys[j];
+    const uint32_t dig = (uint32_t)(k >> shift) & 0xffu;
+    const uint64_t out = gbase[dig] + (uint64_t)(j - (int)tstart[dig]);
+    if (out < (uint64_t)P) {
+      kout[out] = k;
+      iout[out] = sidx[j];
+    }
+  }
+}
+
+}  // namespace
+
+template <class T>
+hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, int64_t N,
+                       hipStream_t s) {
+  constexpr int D = KeyOf<T>::kDigits;
+  const int64_t P = M + N;
+  const size_t words = w.zero_bytes / 4;
+  hipLaunchKernelGGL(k_clear, dim3((unsigned)((words + 255) / 256 < 4096 ? (words + 255) / 256 : 4096)),
+                     dim3(256), 0, s, w.status, words);
+  int64_t hb = (P + 256 * 16 - 1) / (256 * 16);
+  if (hb > kHistBlocks) hb = kHistBlocks;
+  if (hb < 1) hb = 1;
+  hipLaunchKernelGGL(k_histogram<T>, dim3((unsigned)hb), dim3(256), 0, s, x, y, N, P, w.hist,
+                     w.status);
+  hipLaunchKernelGGL(k_plan<T>, dim3(1), dim3(256), 0, s, w.hist, P, w.dig_off, w.pass);
+  for (int d = 0; d < D; ++d) {
+    hipLaunchKernelGGL(k_onesweep<T>, dim3((unsigned)w.sort_tiles), dim3(kSortThreads), 0, s, d, x,
+                       y, N, P, w.keys[0], w.keys[1], w.idx[0], w.idx[1], w.dig_off, w.pass,
+                       w.tile_ctr, w.lookback[d & 1], w.lookback[(d + 1) & 1], w.status);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t sort_points<double>(const Workspace&, const double*, int64_t, const double*,
+                                        int64_t, hipStream_t);
+template hipError_t sort_points<float>(const Workspace&, const float*, int64_t, const float*,
+                                       int64_t, hipStream_t);
+
+}  // namespace fgt

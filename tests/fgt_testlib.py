@@ -1,0 +1,61 @@
+"""Helpers shared by the GPU tests: run the HIP path, run the oracle, compare."""
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+import oracle
+import paper_1909_09825_amd as fgt
+from conftest import load_oracle_tables
+
+OTABLES = load_oracle_tables()
+EPS64 = 2.0 ** -53
+EPS32 = 2.0 ** -24
+
+
+def say(msg: str) -> None:
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def gpu_eval(x, y, alpha, delta, digits, dtype=torch.float64, case=""):
+    """Run fgt_eval through the C ABI; returns (u as float64 numpy, plan, device status)."""
+    say(f"[gpu] fgt_eval {case} M={len(x)} N={len(y)} delta={delta:g} digits={digits} {dtype}")
+    p = fgt.plan(delta, digits, dtype)
+    X, Y, A = to_dev(x, dtype), to_dev(y, dtype), to_dev(alpha, dtype)
+    ws = fgt.workspace(p, len(x), len(y), X.device)
+    u = fgt.eval(X, Y, A, p, ws=ws)
+    status = fgt.last_device_status(ws)
+    return u.double().cpu().numpy(), p, status
+
+
+def oracle_table(p):
+    """The oracle's own table with the plan's mode count."""
+    return OTABLES[p.n_modes]
+
+
+def impl_tol(alpha, p, P, eps=EPS64):
+    """Tolerance for GPU vs the oracle's SOE recurrence (same table, different
+    summation order): each of the ~2 log2(P) levels of the scan and the
+    sequential sweeps adds a few rounding errors of size eps |omega_k| |alpha|;
+    the recurrences damp, never amplify (|e| <= 1)."""
+    s_alpha = float(np.sum(np.abs(alpha)))
+    s_omega = float(np.sum(np.abs(p.omega)))
+    return 64.0 * eps * s_alpha * s_omega * max(1.0, math.log2(max(P, 2)))
+
+
+def check_direct(u, x_sel, y, alpha, delta, p, factor=2.0):
+    """|u - O1| <= factor * E_n * sum|alpha| at the selected targets."""
+    t0 = time.time()
+    ref = oracle.direct(x_sel, y, alpha, delta)
+    s_alpha = float(np.sum(np.abs(alpha)))
+    err = float(np.max(np.abs(u - ref))) / s_alpha if len(u) else 0.0
+    say(f"   O1 check: max err / sum|alpha| = {err:.3e}  (bound {factor} E = {factor * p.err_bound:.3e}, "
+        f"{len(x_sel)} targets, {time.time() - t0:.1f}s)")
+    return err, ref

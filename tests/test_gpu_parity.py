@@ -1,0 +1,141 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+* O1 (direct Gaussian sum): |u - u_O1| <= 2 E_n sum|alpha|, the tolerance
+  the transform is specified to meet (E_n = the plan's stated table error).
+* O2 (the oracle's SOE recurrence with its own, independently built table of
+  the same mode count): agreement to rounding, see fgt_testlib.impl_tol.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1909_09825_amd as fgt
+from paper_1909_09825_amd import workloads as W
+from fgt_testlib import EPS32, check_direct, gpu_eval, impl_tol, oracle_table, say
+
+pytestmark = pytest.mark.gpu
+
+
+def full_check(x, y, a, delta, digits, case, direct=True):
+    u, p, st = gpu_eval(x, y, a, delta, digits, case=case)
+    assert st == fgt.FGT_OK
+    t = oracle_table(p)
+    u2 = oracle.soe_recurrence(x, y, a, delta, t["tau0"], t["omega"])
+    e2 = float(np.max(np.abs(u - u2))) if len(u) else 0.0
+    tol = impl_tol(a, p, len(x) + len(y))
+    say(f"   O2 check: max |u - u_O2| = {e2:.3e} (tol {tol:.3e})")
+    assert e2 <= tol
+    if direct:
+        e1, _ = check_direct(u, x, y, a, delta, p)
+        assert e1 <= 2 * p.err_bound
+    return u, p
+
+
+def test_small_config():
+    """1000 targets, 1000 sources uniform on [0,1), alpha ~ N(0,1), delta 1e-3, 6 digits."""
+    pr = W.small_plain()
+    full_check(pr.x, pr.y, pr.alpha, pr.delta, pr.digits, "small")
+
+
+@pytest.mark.parametrize("digits", [3, 6, 9])
+@pytest.mark.parametrize("delta", [1e-6, 1e-3, 1.0])
+def test_ragged_multi_tile(delta, digits):
+    """Several sort and scan tiles plus a ragged tail, M != N."""
+    pr = W.plain(20011, 30007, delta, digits, cfg=10, sub=int(digits))
+    full_check(pr.x, pr.y, pr.alpha, delta, digits, "ragged", direct=True)
+
+
+@pytest.mark.parametrize("M,N", [(1, 1), (1, 4097), (4097, 1), (2048, 2048), (4096, 4096),
+                                 (2047, 2050), (12288, 4096)])
+def test_shapes(M, N):
+    pr = W.plain(M, N, 1e-3, 6, cfg=11, sub=M % 97)
+    full_check(pr.x, pr.y, pr.alpha, 1e-3, 6, f"shape{M}x{N}")
+
+
+def test_no_sources_gives_zero():
+    say("[gpu] N = 0")
+    p = fgt.plan(1e-3, 6)
+    x = torch.rand(100, dtype=torch.float64, device="cuda")
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    u = fgt.eval(x, e, e, p, out=torch.full((100,), 7.0, dtype=torch.float64, device="cuda"))
+    assert torch.all(u == 0)
+
+
+def test_no_targets():
+    say("[gpu] M = 0")
+    p = fgt.plan(1e-3, 6)
+    y = torch.rand(100, dtype=torch.float64, device="cuda")
+    u = fgt.eval(torch.empty(0, dtype=torch.float64, device="cuda"), y, y, p)
+    assert u.numel() == 0
+
+
+def test_all_coordinates_equal():
+    x = np.full(3000, 0.25)
+    y = np.full(5000, 0.25)
+    a = np.random.default_rng(1).standard_normal(5000)
+    u, p = full_check(x, y, a, 1e-2, 6, "all-equal")
+    s0 = float(np.sum(oracle_table(p)["omega"]).real)
+    np.testing.assert_allclose(u, s0 * np.sum(a), rtol=0, atol=1e-12 * np.sum(np.abs(a)))
+
+
+def test_ties_duplicates_negative_and_signed_zero():
+    g = np.random.default_rng(2)
+    grid = np.arange(-300, 301) / 256.0
+    y = np.concatenate([g.choice(grid, 9000), [0.0, -0.0, 0.0]])
+    x = np.concatenate([g.choice(y, 4000), g.choice(grid, 3000), [-0.0, 0.0]])
+    a = g.standard_normal(len(y))
+    full_check(x, y, a, 1e-4, 9, "ties")
+
+
+def test_wide_spread_small_delta():
+    """Gaps far beyond the decay length: exponentials underflow, general exp path."""
+    g = np.random.default_rng(3)
+    y = g.uniform(-1e6, 1e6, 20000)
+    x = np.concatenate([y[:500] + g.normal(0, 1e-4, 500), g.uniform(-1e6, 1e6, 9500)])
+    a = g.standard_normal(len(y))
+    full_check(x, y, a, 1e-6, 6, "spread")
+
+
+def test_clustered_small():
+    pr = W.clustered(log2n=15, log2m=13, delta=1e-5, digits=6, n_comp=16)
+    full_check(pr.x, pr.y, pr.alpha, pr.delta, 6, "clustered-small")
+
+
+def test_deterministic():
+    pr = W.plain(50000, 60000, 1e-4, 6, cfg=12)
+    u1, _, _ = gpu_eval(pr.x, pr.y, pr.alpha, 1e-4, 6, case="det-1")
+    u2, _, _ = gpu_eval(pr.x, pr.y, pr.alpha, 1e-4, 6, case="det-2")
+    assert np.array_equal(u1.view(np.int64), u2.view(np.int64))
+
+
+def test_nonfinite_is_reported():
+    x = np.random.default_rng(4).random(1000)
+    y = np.random.default_rng(5).random(1000)
+    x[17] = np.nan
+    _, _, st = gpu_eval(x, y, np.ones(1000), 1e-3, 6, case="nan")
+    assert st == fgt.FGT_ENONFINITE
+    y[3] = np.inf
+    x[17] = 0.5
+    _, _, st = gpu_eval(x, y, np.ones(1000), 1e-3, 6, case="inf")
+    assert st == fgt.FGT_ENONFINITE
+
+
+@pytest.mark.parametrize("digits", [3, 4, 6])
+def test_fp32(digits):
+    """FP32 inputs (the FP32-rounded values, cast exactly to FP64 for the oracle).
+
+    Stated error: E_n plus FP32 rounding of the recurrences, bounded here by
+    E_n + 64 eps32 sum|omega| (relative to sum|alpha|)."""
+    pr = W.plain(30001, 40003, 1e-4, digits, cfg=13, sub=digits)
+    x32 = pr.x.astype(np.float32)
+    y32 = pr.y.astype(np.float32)
+    a32 = pr.alpha.astype(np.float32)
+    u, p, st = gpu_eval(x32, y32, a32, 1e-4, digits, dtype=torch.float32, case="fp32")
+    assert st == fgt.FGT_OK
+    ref = oracle.direct(x32.astype(np.float64), y32.astype(np.float64), a32.astype(np.float64), 1e-4)
+    s_alpha = float(np.sum(np.abs(a32.astype(np.float64))))
+    err = float(np.max(np.abs(u - ref))) / s_alpha
+    bound = p.err_bound + 64 * EPS32 * float(np.sum(np.abs(p.omega)))
+    say(f"   FP32 error / sum|alpha| = {err:.3e} (E = {p.err_bound:.2e}, bound {bound:.2e})")
+    assert err <= bound
