@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the 1-D fast Gauss transform on one MI355X.
+
+One step = one fgt_eval over the whole hot path (key build, radix sort,
+tile-scan reduce, carries, fused forward/backward sweeps, mode reduction and
+scatter) for M = N = 2^24 points uniform on [0,1), alpha ~ N(0,1),
+delta = 1e-4, 6 digits (4 modes), FP64, with inputs resident in HBM.
+
+Prints ONE JSON line.  `value` is (M+N) * modes / s.  `roofline` describes
+the kernel with the largest share of the step, timed with HIP events recorded
+by the library on its own stream during the timed steps; `cpu_baseline` is
+the CPU oracle's SOE recurrence timed on a bounded sample of the same inputs.
+
+    python bench.py [--steps K] [--warmup W] [--delta D] [--digits G] [--log2n L]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
+METRIC = "(M+N)·modes/s and transforms/s at 6 digits, fwd vs fwd+bwd, % HBM roofline"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--delta", type=float, default=1e-4)
+    ap.add_argument("--digits", type=int, default=6)
+    ap.add_argument("--log2n", type=int, default=24, help="M = N = 2^log2n")
+    ap.add_argument("--fp32", action="store_true", help="time the FP32 path instead")
+    ap.add_argument("--cpu-sample-log2n", type=int, default=22,
+                    help="CPU oracle timed on the first 2^k targets and sources")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also run one plain device copy of this many bytes (counter calibration)")
+    return ap.parse_args()
+
+
+def source_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch from committed counter runs, if the kernel source is unchanged."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha") != source_hash(rec["sources"]):
+        return None
+    return rec["bytes_per_launch"]
+
+
+def cpu_baseline(x, y, a, delta, digits, n_modes, k):
+    """The CPU oracle's SOE recurrence (sort + per-mode sweeps) on the first 2^k points."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import oracle
+    from conftest import load_oracle_tables
+    t = load_oracle_tables()[n_modes]
+    n = 1 << k
+    xs, ys, as_ = x[:n].copy(), y[:n].copy(), a[:n].copy()
+    t0 = time.perf_counter()
+    oracle.soe_recurrence(xs, ys, as_, delta, t["tau0"], t["omega"])
+    dt = time.perf_counter() - t0
+    threads = oracle.max_threads()
+    return {
+        "value": (2 * n) * n_modes / dt, "unit": "point-modes/s",
+        "cores": int(min(threads, 2 * n_modes)), "kind": "oracle",
+        "sample": (f"first 2^{k} targets and 2^{k} sources of the same inputs, {digits} digits "
+                   f"({n_modes} modes): O2 SOE recurrence in C (qsort, then one sweep per mode and "
+                   f"direction, OpenMP over the {2 * n_modes} sweeps), {dt:.2f} s wall"),
+    }
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (requested --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the transform is not sharded across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1909_09825_amd as fgt
+    from paper_1909_09825_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dtype = torch.float32 if args.fp32 else torch.float64
+    pr = W.large_plain(args.delta, args.digits, args.log2n)
+    M, N = pr.M, pr.N
+    P = M + N
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(pr.x).to(dev, dtype)
+    Y = torch.from_numpy(pr.y).to(dev, dtype)
+    A = torch.from_numpy(pr.alpha).to(dev, dtype)
+    p = fgt.plan(args.delta, args.digits, dtype)
+    ws = fgt.workspace(p, M, N, dev)
+    u = torch.empty(M, dtype=dtype, device=dev)
+
+    for _ in range(args.warmup):
+        fgt.eval(X, Y, A, p, out=u, ws=ws)
+    torch.cuda.synchronize()
+    status = fgt.last_device_status(ws)
+    if status != fgt.FGT_OK:
+        raise RuntimeError(f"device status {status} after warmup")
+
+    fgt.profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fgt.eval(X, Y, A, p, out=u, ws=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases, calls = fgt.profile_end()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+
+    if args.copy_bytes > 0:
+        src = torch.empty(args.copy_bytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    esz = 4 if args.fp32 else 8
+    n_modes = p.n_modes
+    per_step = {k: v / calls for k, v in phases.items()}
+    radix = {k: v for k, v in per_step.items() if k.startswith("radix")}
+    groups = {
+        "k_onesweep": sum(radix.values()),
+        "k_tiles_final": per_step.get("tiles_final", 0.0),
+        "k_tiles_reduce": per_step.get("tiles_reduce", 0.0),
+        "setup": per_step.get("setup", 0.0),
+        "k_carry": per_step.get("carry", 0.0),
+    }
+    dominant = max(groups, key=groups.get)
+    # Algorithmic bytes per launch.
+    n_passes = len(radix)
+    sort_bytes_first = P * (esz + esz + 4)          # read coordinate, write key + index
+    sort_bytes_rest = P * 2 * (esz + 4)             # read and write key + index
+    scan_read = P * (esz + 4) + N * esz             # keys + index, gathered alpha
+    alg = {
+        "k_onesweep": (sort_bytes_first + (n_passes - 1) * sort_bytes_rest) / max(n_passes, 1),
+        "k_tiles_final": scan_read + M * esz,        # + u scattered
+        "k_tiles_reduce": scan_read,
+    }
+    launches = {"k_onesweep": n_passes, "k_tiles_final": 1, "k_tiles_reduce": 1}
+
+    def roof(kernel):
+        ms_launch = groups[kernel] / launches[kernel]
+        gbs = alg[kernel] / (ms_launch * 1e-3) / 1e9
+        return gbs, ms_launch
+
+    dom = dominant if dominant in alg else "k_onesweep"
+    gbs, ms_launch = roof(dom)
+    traffic = traffic_for(dom)
+    kernels = {}
+    for k in ("k_onesweep", "k_tiles_reduce", "k_tiles_final"):
+        g, ms = roof(k)
+        kernels[k] = {"ms_per_launch": round(ms, 5), "launches_per_step": launches[k],
+                      "alg_bytes_per_launch": int(alg[k]), "GBps": round(g, 1),
+                      "hbm_frac": round(g / HBM_PEAK_GBS, 4)}
+    out = {
+        "metric": METRIC,
+        "value": P * n_modes / (ms_step * 1e-3),
+        "unit": "point-modes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.fp32 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"plain FGT, M = N = 2^{args.log2n} uniform on [0,1), alpha ~ N(0,1), "
+                         f"delta = {args.delta:g}, {args.digits} digits ({n_modes} modes), forward"),
+            "M": M, "N": N, "delta": args.delta, "digits": args.digits, "n_modes": n_modes,
+            "transforms_per_s": 1e3 / ms_step,
+            "phase_ms_per_step": {k: round(v, 5) for k, v in per_step.items()},
+            "kernels": kernels,
+        },
+        "roofline": {
+            "kernel": dom,
+            "bound": "hbm",
+            "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pr.x, pr.y, pr.alpha, args.delta, args.digits, n_modes,
+                                           min(args.cpu_sample_log2n, args.log2n))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -21,7 +21,7 @@
  *     for FGT_F32); the caller owns them.  Inputs are only read.
  *   - Work is enqueued on `stream` and the call returns without synchronising;
  *     nothing is allocated on the device by fgt_eval.
- *   - Return value: FGT_OK or a negative-free error code below.  A call that
+ *   - Return value: FGT_OK or one of the positive error codes below.  A call that
  *     returns an error has enqueued nothing.
  *   - Sizes are element counts.  M + N must be below 2^32.
  */
@@ -120,6 +120,18 @@ int fgt_eval(fgt_plan_t plan, const void* x, int64_t M, const void* y, const voi
  * Returns FGT_OK, FGT_ENONFINITE, or FGT_EINVAL / FGT_EDEVICE.
  */
 int fgt_last_device_status(void* ws, hipStream_t stream);
+
+/*
+ * Phase timing for benchmarks.  Between fgt_profile_begin and fgt_profile_end
+ * every fgt_eval records HIP events on its own stream around each kernel
+ * group (phase names: fgt_profile_phase_name).  fgt_profile_end waits for the
+ * recorded events and returns, per phase, the milliseconds summed over the
+ * calls (ms[max_phases], host memory), the number of phases and of calls.
+ * Not thread-safe; meant for single-threaded benchmark drivers.
+ */
+int fgt_profile_begin(void);
+int fgt_profile_end(double* ms, int max_phases, int* n_phases, int* n_calls);
+const char* fgt_profile_phase_name(int phase);
 
 /* Human-readable text for a status code (static storage). */
 const char* fgt_strerror(int status);

@@ -8,8 +8,9 @@ of include/fgt.h.
 """
 from ._lib import (FGT_EDEVICE, FGT_EINVAL, FGT_ENONFINITE, FGT_EUNSUPPORTED, FGT_F32, FGT_F64,
                    FGT_OK, FGTError, LIB_PATH)
-from .api import Plan, eval, last_device_status, max_digits, plan, workspace
+from .api import (Plan, eval, last_device_status, max_digits, plan, profile_begin, profile_end,
+                  workspace)
 
 __all__ = ["Plan", "plan", "eval", "workspace", "last_device_status", "max_digits", "FGTError",
            "FGT_OK", "FGT_EINVAL", "FGT_EUNSUPPORTED", "FGT_ENONFINITE", "FGT_EDEVICE",
-           "FGT_F64", "FGT_F32", "LIB_PATH"]
+           "FGT_F64", "FGT_F32", "LIB_PATH", "profile_begin", "profile_end"]

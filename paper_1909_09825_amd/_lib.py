@@ -49,6 +49,12 @@ def load() -> ctypes.CDLL:
     lib.fgt_last_device_status.restype = c_int
     lib.fgt_strerror.argtypes = [c_int]
     lib.fgt_strerror.restype = ctypes.c_char_p
+    lib.fgt_profile_begin.argtypes = []
+    lib.fgt_profile_begin.restype = c_int
+    lib.fgt_profile_end.argtypes = [dp, c_int, ip, ip]
+    lib.fgt_profile_end.restype = c_int
+    lib.fgt_profile_phase_name.argtypes = [c_int]
+    lib.fgt_profile_phase_name.restype = ctypes.c_char_p
     lib.fgt_version.argtypes = []
     lib.fgt_version.restype = ctypes.c_char_p
     _lib = lib

@@ -129,3 +129,22 @@ def last_device_status(ws: torch.Tensor) -> int:
     """Synchronise the current stream; return and clear the device status of `ws` (0 = ok)."""
     stream = torch.cuda.current_stream(ws.device).cuda_stream
     return int(_lib.load().fgt_last_device_status(ws.data_ptr(), stream))
+
+
+def profile_begin() -> None:
+    """Record per-phase HIP events in subsequent eval calls (benchmark use)."""
+    check(_lib.load().fgt_profile_begin(), "fgt_profile_begin")
+
+
+def profile_end() -> tuple[dict, int]:
+    """Stop recording; return ({phase: summed ms}, number of calls)."""
+    lib = _lib.load()
+    ms = (ctypes.c_double * 16)()
+    n_ph, n_calls = ctypes.c_int(), ctypes.c_int()
+    check(lib.fgt_profile_end(ms, 16, ctypes.byref(n_ph), ctypes.byref(n_calls)), "fgt_profile_end")
+    out = {}
+    for i in range(n_ph.value):
+        name = lib.fgt_profile_phase_name(i).decode()
+        if ms[i] > 0:
+            out[name] = ms[i]
+    return out, n_calls.value

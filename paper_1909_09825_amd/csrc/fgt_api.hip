@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "fgt_internal.h"
 
@@ -63,6 +64,18 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   w.total = off;
   return w;
 }
+
+// Benchmark timing state (see fgt_profile_begin).
+struct Profiler {
+  bool on = false;
+  struct Call {
+    hipEvent_t ev[kMaxPhases + 1];
+    int n;
+    bool f64;
+  };
+  std::vector<Call> calls;
+};
+static Profiler g_prof;
 
 }  // namespace fgt
 
@@ -175,17 +188,77 @@ int fgt_eval(fgt_plan_t plan, const void* x, int64_t M, const void* y, const voi
   const int esz = f64 ? 8 : 4;
   const fgt::Workspace w = fgt::layout(ws, M + N, esz, plan->modes.n);
   if (ws_bytes < w.total) return FGT_EINVAL;
+  fgt::Timeline tl;
+  fgt::Profiler::Call call;
+  if (fgt::g_prof.on) {
+    call.n = 0;
+    call.f64 = f64;
+    for (int i = 0; i <= fgt::kMaxPhases; ++i) {
+      if (hipEventCreate(&call.ev[i]) != hipSuccess) return FGT_EDEVICE;
+    }
+    tl.ev = call.ev;
+    tl.cap = fgt::kMaxPhases + 1;
+  }
   hipError_t e;
   if (f64) {
-    e = fgt::sort_points<double>(w, (const double*)x, M, (const double*)y, N, stream);
+    e = fgt::sort_points<double>(w, (const double*)x, M, (const double*)y, N, stream, &tl);
     if (e == hipSuccess)
-      e = fgt::scan_points<double>(w, plan->modes, (const double*)alpha, M, N, (double*)u, stream);
+      e = fgt::scan_points<double>(w, plan->modes, (const double*)alpha, M, N, (double*)u, stream,
+                                   &tl);
   } else {
-    e = fgt::sort_points<float>(w, (const float*)x, M, (const float*)y, N, stream);
+    e = fgt::sort_points<float>(w, (const float*)x, M, (const float*)y, N, stream, &tl);
     if (e == hipSuccess)
-      e = fgt::scan_points<float>(w, plan->modes, (const float*)alpha, M, N, (float*)u, stream);
+      e = fgt::scan_points<float>(w, plan->modes, (const float*)alpha, M, N, (float*)u, stream,
+                                  &tl);
+  }
+  if (fgt::g_prof.on) {
+    call.n = tl.n;
+    fgt::g_prof.calls.push_back(call);
   }
   return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+}
+
+int fgt_profile_begin(void) {
+  fgt::g_prof.on = true;
+  return FGT_OK;
+}
+
+static const char* const kPhaseNamesF64[] = {"setup", "radix0", "radix1", "radix2", "radix3",
+                                             "radix4", "radix5", "radix6", "radix7",
+                                             "tiles_reduce", "carry", "tiles_final"};
+
+const char* fgt_profile_phase_name(int phase) {
+  if (phase < 0 || phase >= fgt::kMaxPhases) return "";
+  return kPhaseNamesF64[phase];
+}
+
+int fgt_profile_end(double* ms, int max_phases, int* n_phases, int* n_calls) {
+  fgt::g_prof.on = false;
+  double acc[fgt::kMaxPhases] = {0};
+  int phases = 0;
+  int rc = FGT_OK;
+  for (auto& c : fgt::g_prof.calls) {
+    // FP32 has 4 radix passes: map its phases onto the FP64 names.
+    const int passes = c.f64 ? 8 : 4;
+    for (int i = 0; i + 1 < c.n; ++i) {
+      float t = 0.f;
+      if (hipEventSynchronize(c.ev[i + 1]) != hipSuccess ||
+          hipEventElapsedTime(&t, c.ev[i], c.ev[i + 1]) != hipSuccess) {
+        rc = FGT_EDEVICE;
+        continue;
+      }
+      const int name = i <= passes ? i : i + (8 - passes);
+      acc[name] += t;
+      if (name + 1 > phases) phases = name + 1;
+    }
+    for (int i = 0; i <= fgt::kMaxPhases; ++i) (void)hipEventDestroy(c.ev[i]);
+  }
+  if (n_calls) *n_calls = (int)fgt::g_prof.calls.size();
+  fgt::g_prof.calls.clear();
+  if (n_phases) *n_phases = phases;
+  if (ms)
+    for (int i = 0; i < max_phases && i < fgt::kMaxPhases; ++i) ms[i] = acc[i];
+  return rc;
 }
 
 int fgt_last_device_status(void* ws, hipStream_t stream) {

@@ -107,6 +107,16 @@ struct Workspace {
   size_t total;
 };
 
+// Phase boundaries for benchmark timing: mark() records the next event, if any.
+constexpr int kMaxPhases = 12;   // setup, 8 radix passes, tile reduce, carry, tile final
+struct Timeline {
+  hipEvent_t* ev = nullptr;
+  int n = 0, cap = 0;
+  void mark(hipStream_t s) {
+    if (ev && n < cap) (void)hipEventRecord(ev[n++], s);
+  }
+};
+
 // Layout for P points, element size `esz` (8 or 4), n_modes modes.  With
 // base == nullptr only sizes are computed.
 Workspace layout(void* base, int64_t P, int esz, int n_modes);
@@ -114,10 +124,10 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes);
 // Kernel launch sequences (defined in the .hip files).
 template <class T>
 hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, int64_t N,
-                       hipStream_t s);
+                       hipStream_t s, Timeline* tl);
 template <class T>
 hipError_t scan_points(const Workspace& w, const Modes& m, const T* alpha, int64_t M, int64_t N,
-                       T* u, hipStream_t s);
+                       T* u, hipStream_t s, Timeline* tl);
 template <class T>
 hipError_t fill_zero(T* u, int64_t n, hipStream_t s);
 

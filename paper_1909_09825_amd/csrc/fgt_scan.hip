@@ -400,15 +400,18 @@ __global__ void k_fill_zero(T* __restrict__ u, int64_t n) {
 
 template <class T, int NM>
 hipError_t scan_nm(const Workspace& w, const Modes& md, const T* alpha, int64_t M, int64_t N, T* u,
-                   hipStream_t s) {
+                   hipStream_t s, Timeline* tl) {
   const int64_t P = M + N;
   const dim3 grid((unsigned)w.scan_tiles);
   hipLaunchKernelGGL((k_tiles<T, NM, false>), grid, dim3(kScanThreads), 0, s, w.keys[0], w.keys[1],
                      w.idx[0], w.idx[1], w.pass, alpha, N, P, md, (T*)w.agg, (const T*)w.carry, u);
+  tl->mark(s);
   hipLaunchKernelGGL((k_carry<T, NM>), dim3(NM), dim3(kCarryThreads), 0, s, (const T*)w.agg,
                      w.scan_tiles, (T*)w.carry);
+  tl->mark(s);
   hipLaunchKernelGGL((k_tiles<T, NM, true>), grid, dim3(kScanThreads), 0, s, w.keys[0], w.keys[1],
                      w.idx[0], w.idx[1], w.pass, alpha, N, P, md, (T*)w.agg, (const T*)w.carry, u);
+  tl->mark(s);
   return hipGetLastError();
 }
 
@@ -416,16 +419,16 @@ hipError_t scan_nm(const Workspace& w, const Modes& md, const T* alpha, int64_t 
 
 template <class T>
 hipError_t scan_points(const Workspace& w, const Modes& md, const T* alpha, int64_t M, int64_t N,
-                       T* u, hipStream_t s) {
+                       T* u, hipStream_t s, Timeline* tl) {
   switch (md.n) {
-    case 1: return scan_nm<T, 1>(w, md, alpha, M, N, u, s);
-    case 2: return scan_nm<T, 2>(w, md, alpha, M, N, u, s);
-    case 3: return scan_nm<T, 3>(w, md, alpha, M, N, u, s);
-    case 4: return scan_nm<T, 4>(w, md, alpha, M, N, u, s);
-    case 5: return scan_nm<T, 5>(w, md, alpha, M, N, u, s);
-    case 6: return scan_nm<T, 6>(w, md, alpha, M, N, u, s);
-    case 7: return scan_nm<T, 7>(w, md, alpha, M, N, u, s);
-    case 8: return scan_nm<T, 8>(w, md, alpha, M, N, u, s);
+    case 1: return scan_nm<T, 1>(w, md, alpha, M, N, u, s, tl);
+    case 2: return scan_nm<T, 2>(w, md, alpha, M, N, u, s, tl);
+    case 3: return scan_nm<T, 3>(w, md, alpha, M, N, u, s, tl);
+    case 4: return scan_nm<T, 4>(w, md, alpha, M, N, u, s, tl);
+    case 5: return scan_nm<T, 5>(w, md, alpha, M, N, u, s, tl);
+    case 6: return scan_nm<T, 6>(w, md, alpha, M, N, u, s, tl);
+    case 7: return scan_nm<T, 7>(w, md, alpha, M, N, u, s, tl);
+    case 8: return scan_nm<T, 8>(w, md, alpha, M, N, u, s, tl);
     default: return hipErrorInvalidValue;
   }
 }
@@ -440,9 +443,9 @@ hipError_t fill_zero(T* u, int64_t n, hipStream_t s) {
 }
 
 template hipError_t scan_points<double>(const Workspace&, const Modes&, const double*, int64_t,
-                                        int64_t, double*, hipStream_t);
+                                        int64_t, double*, hipStream_t, Timeline*);
 template hipError_t scan_points<float>(const Workspace&, const Modes&, const float*, int64_t,
-                                       int64_t, float*, hipStream_t);
+                                       int64_t, float*, hipStream_t, Timeline*);
 template hipError_t fill_zero<double>(double*, int64_t, hipStream_t);
 template hipError_t fill_zero<float>(float*, int64_t, hipStream_t);
 

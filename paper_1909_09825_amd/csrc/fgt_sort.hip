@@ -301,9 +301,10 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(
 
 template <class T>
 hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, int64_t N,
-                       hipStream_t s) {
+                       hipStream_t s, Timeline* tl) {
   constexpr int D = KeyOf<T>::kDigits;
   const int64_t P = M + N;
+  tl->mark(s);
   const size_t words = w.zero_bytes / 4;
   hipLaunchKernelGGL(k_clear, dim3((unsigned)((words + 255) / 256 < 4096 ? (words + 255) / 256 : 4096)),
                      dim3(256), 0, s, w.status, words);
@@ -313,17 +314,19 @@ hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, in
   hipLaunchKernelGGL(k_histogram<T>, dim3((unsigned)hb), dim3(256), 0, s, x, y, N, P, w.hist,
                      w.status);
   hipLaunchKernelGGL(k_plan<T>, dim3(1), dim3(256), 0, s, w.hist, P, w.dig_off, w.pass);
+  tl->mark(s);
   for (int d = 0; d < D; ++d) {
     hipLaunchKernelGGL(k_onesweep<T>, dim3((unsigned)w.sort_tiles), dim3(kSortThreads), 0, s, d, x,
                        y, N, P, w.keys[0], w.keys[1], w.idx[0], w.idx[1], w.dig_off, w.pass,
                        w.tile_ctr, w.lookback[d & 1], w.lookback[(d + 1) & 1], w.status);
+    tl->mark(s);
   }
   return hipGetLastError();
 }
 
 template hipError_t sort_points<double>(const Workspace&, const double*, int64_t, const double*,
-                                        int64_t, hipStream_t);
+                                        int64_t, hipStream_t, Timeline*);
 template hipError_t sort_points<float>(const Workspace&, const float*, int64_t, const float*,
-                                       int64_t, hipStream_t);
+                                       int64_t, hipStream_t, Timeline*);
 
 }  // namespace fgt
