@@ -48,6 +48,7 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   // The region cleared at the start of each call is contiguous: status word
   // (always at offset 0), histograms, tile counters and the first look-back buffer.
   w.status = (uint32_t*)take(sizeof(uint32_t) * 64);
+  w.maxabs = (unsigned long long*)take(sizeof(unsigned long long));
   w.hist = (uint32_t*)take(sizeof(uint32_t) * digits * kRadix);
   w.tile_ctr = (uint32_t*)take(sizeof(uint32_t) * 8);
   w.lookback[0] = (uint64_t*)take(sizeof(uint64_t) * (size_t)w.sort_tiles * kRadix);
@@ -61,6 +62,8 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   w.keys[1] = take((size_t)esz * (size_t)P);
   w.idx[0] = (uint32_t*)take(sizeof(uint32_t) * (size_t)P);
   w.idx[1] = (uint32_t*)take(sizeof(uint32_t) * (size_t)P);
+  w.b = take((size_t)esz * (size_t)P);
+  w.slot = (uint32_t*)take(sizeof(uint32_t) * (size_t)P);
   w.total = off;
   return w;
 }
@@ -130,13 +133,48 @@ int fgt_plan(double delta, int digits, int dtype, fgt_plan_t* out) {
   memset(&p->modes, 0, sizeof(p->modes));
   p->modes.n = tab->n_modes;
   const double rs = 1.0 / sqrt(delta);
+  p->modes.tau_abs_max = 0.0;
   for (int k = 0; k < tab->n_modes; ++k) {
     p->modes.tau_re[k] = tab->tau0_re[k] * rs;
     p->modes.tau_im[k] = tab->tau0_im[k] * rs;
     p->modes.om_re[k] = tab->om_re[k];
     p->modes.om_im[k] = tab->om_im[k];
-    const double mag = hypot(p->modes.tau_re[k], p->modes.tau_im[k]);
-    p->modes.dz_fast[k] = fgt::kFastR / mag;
+    p->modes.tau_abs[k] = hypot(p->modes.tau_re[k], p->modes.tau_im[k]);
+    if (p->modes.tau_abs[k] > p->modes.tau_abs_max) p->modes.tau_abs_max = p->modes.tau_abs[k];
+  }
+  // Sort resolution.  Two points closer than w = s_w sqrt(delta) may be left in
+  // either order.  If a source at y and a target at x swap places, x - y
+  // changes sign and the recurrences evaluate S at -|x - y| instead of
+  // +|x - y| (continued through the same exponentials); with s = |x - y| /
+  // sqrt(delta) the change is |Re sum omega (e^{tau0 s} - e^{-tau0 s})| <=
+  // 2 |Re sum omega tau0| s + (1/3) sum |omega| |tau0|^3 s^3 cosh(max|tau0| s).
+  // s_w makes this at most 1e-6 E_n, so the result stays within
+  // (1 + 1e-6) E_n sum|alpha| of the Gauss transform.
+  {
+    double slope = 0.0, c3 = 0.0, tmax = 0.0;
+    for (int k = 0; k < tab->n_modes; ++k) {
+      slope += tab->om_re[k] * tab->tau0_re[k] - tab->om_im[k] * tab->tau0_im[k];
+      const double ta = hypot(tab->tau0_re[k], tab->tau0_im[k]);
+      c3 += hypot(tab->om_re[k], tab->om_im[k]) * ta * ta * ta;
+      if (ta > tmax) tmax = ta;
+    }
+    slope = fabs(slope);
+    const double target = 1e-6 * tab->err_bound;
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 200; ++it) {
+      const double s = 0.5 * (lo + hi);
+      const double b = 2.0 * slope * s + c3 * s * s * s * cosh(tmax * s) / 3.0;
+      if (b <= target) lo = s; else hi = s;
+    }
+    p->modes.key_width = lo * sqrt(delta);
+  }
+  // Taylor thresholds for the element type's unit roundoff.
+  const double unit = dtype == FGT_F64 ? ldexp(1.0, -53) : ldexp(1.0, -24);
+  double fact = 1.0;
+  p->modes.taylor_thr[0] = 0.0;
+  for (int d = 1; d <= fgt::kTaylorMax; ++d) {
+    fact *= (d + 1);   // (d+1)!
+    p->modes.taylor_thr[d] = pow(unit * fact, 1.0 / (d + 1));
   }
   *out = p;
   return FGT_OK;
@@ -201,15 +239,13 @@ int fgt_eval(fgt_plan_t plan, const void* x, int64_t M, const void* y, const voi
   }
   hipError_t e;
   if (f64) {
-    e = fgt::sort_points<double>(w, (const double*)x, M, (const double*)y, N, stream, &tl);
-    if (e == hipSuccess)
-      e = fgt::scan_points<double>(w, plan->modes, (const double*)alpha, M, N, (double*)u, stream,
-                                   &tl);
+    e = fgt::sort_points<double>(w, (const double*)x, M, (const double*)y, (const double*)alpha, N,
+                                 plan->modes.key_width, stream, &tl);
+    if (e == hipSuccess) e = fgt::scan_points<double>(w, plan->modes, M, N, (double*)u, stream, &tl);
   } else {
-    e = fgt::sort_points<float>(w, (const float*)x, M, (const float*)y, N, stream, &tl);
-    if (e == hipSuccess)
-      e = fgt::scan_points<float>(w, plan->modes, (const float*)alpha, M, N, (float*)u, stream,
-                                  &tl);
+    e = fgt::sort_points<float>(w, (const float*)x, M, (const float*)y, (const float*)alpha, N,
+                                plan->modes.key_width, stream, &tl);
+    if (e == hipSuccess) e = fgt::scan_points<float>(w, plan->modes, M, N, (float*)u, stream, &tl);
   }
   if (fgt::g_prof.on) {
     call.n = tl.n;

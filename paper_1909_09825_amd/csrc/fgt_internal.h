@@ -19,13 +19,22 @@ struct SoeTable {
   double err_bound, deriv_err_bound, sum_abs_omega;
 };
 
+// Highest Taylor degree of the mode exponential and highest power moment.
+constexpr int kTaylorMax = 12;
+constexpr int kMomentMax = 20;
+
 // Passed by value to the scan kernels: tau_k = tau0_k / sqrt(delta), omega_k,
-// and the fast-exponential threshold dz_fast_k = R / |tau_k| (see exp_neg).
+// |tau_k|, max_k |tau_k|, and the Taylor thresholds of the plan's precision:
+// degree D is enough for exp(-w) when |w| <= taylor_thr[D], i.e.
+// taylor_thr[D]^{D+1} / (D+1)! equals the unit roundoff.
 struct Modes {
   int n;
   double tau_re[FGT_MAX_MODES], tau_im[FGT_MAX_MODES];
   double om_re[FGT_MAX_MODES], om_im[FGT_MAX_MODES];
-  double dz_fast[FGT_MAX_MODES];
+  double tau_abs[FGT_MAX_MODES];
+  double tau_abs_max;
+  double taylor_thr[kTaylorMax + 1];
+  double key_width;   // sort resolution in coordinate units (see fgt_plan)
 };
 
 // ---------------------------------------------------------------------------
@@ -34,7 +43,7 @@ struct Modes {
 constexpr int kWave = 64;
 
 // LSD radix sort: 8-bit digits, one-sweep passes with decoupled look-back.
-constexpr int kSortThreads = 256;
+constexpr int kSortThreads = 512;
 constexpr int kSortWaves = kSortThreads / kWave;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per tile
@@ -48,8 +57,6 @@ constexpr int kScanChunk = 8;
 constexpr int kScanTile = kScanThreads * kScanChunk;   // 2048 points per tile
 constexpr int kCarryThreads = 1024;
 
-// Radius of the Taylor branch of the mode exponential: |tau dz| <= kFastR.
-constexpr double kFastR = 1.0 / 16.0;
 
 template <class T> struct KeyOf;
 template <> struct KeyOf<double> { using type = uint64_t; static constexpr int kDigits = 8; };
@@ -77,6 +84,9 @@ __device__ __forceinline__ float from_key(uint32_t k) {
   return __uint_as_float(b);
 }
 
+// Slot value of a source in the sorted sequence.
+constexpr uint32_t kNoSlot = 0xffffffffu;
+
 // Bits of the device status word.
 constexpr uint32_t kStatusNonFinite = 1u;
 constexpr uint32_t kStatusInternal = 2u;
@@ -88,13 +98,18 @@ struct PassInfo {
   int32_t run[8];     // 1 if radix pass d moves data
   int32_t src[8];     // 0/1: key buffer it reads, 2: the raw coordinates
   int32_t final_buf;  // buffer that holds the sorted keys at the end
-  int32_t pad[7];
+  int32_t last_pass;  // the last pass that runs; it also writes strengths and slots
+  int32_t skipped_low;  // low digits left unsorted (below the plan's key resolution)
+  int32_t pad[5];
 };
 
 struct Workspace {
   void* keys[2];
   uint32_t* idx[2];
+  void* b;               // [P] strength of each sorted point (alpha_j for a source, 0 for a target)
+  uint32_t* slot;        // [P] output index of each sorted target, kNoSlot for a source
   uint32_t* status;      // [1] at offset 0, zeroed per call
+  unsigned long long* maxabs;  // [1] largest |coordinate| as ordered bits, zeroed per call
   uint32_t* hist;        // [digits][256], zeroed per call
   uint32_t* tile_ctr;    // [8], zeroed per call
   uint64_t* lookback[2]; // [sort_tiles][256]; [0] zeroed per call, each pass clears the other
@@ -122,12 +137,14 @@ struct Timeline {
 Workspace layout(void* base, int64_t P, int esz, int n_modes);
 
 // Kernel launch sequences (defined in the .hip files).
+// key_width: coordinate differences below it may be left unordered (see
+// the plan's key resolution); 0 sorts every digit.
 template <class T>
-hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, int64_t N,
+hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, const T* alpha,
+                       int64_t N, double key_width, hipStream_t s, Timeline* tl);
+template <class T>
+hipError_t scan_points(const Workspace& w, const Modes& m, int64_t M, int64_t N, T* u,
                        hipStream_t s, Timeline* tl);
-template <class T>
-hipError_t scan_points(const Workspace& w, const Modes& m, const T* alpha, int64_t M, int64_t N,
-                       T* u, hipStream_t s, Timeline* tl);
 template <class T>
 hipError_t fill_zero(T* u, int64_t n, hipStream_t s);
 

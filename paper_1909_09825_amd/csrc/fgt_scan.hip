@@ -12,16 +12,20 @@
 //
 // A segment [s, e) of the sequence acts on the two recurrences as
 //     h+_{e-1} = A h+_{s-1} + F,          h-_{s-1} = A h-_{e-1} + G,
-//     A = prod_{p in seg} e_p,  F = sum b_q e^{-tau (z_{e-1} - z_q)},  G = sum b_q e^{-tau (z_q - z_{s-1})},
+//     A = prod_{p in seg} e_p = exp(-tau (z_{e-1} - z_{s-1})),
+//     F = sum_{q in seg} b_q exp(-tau (z_{e-1} - z_q)),   G = sum_{q in seg} b_q exp(-tau (z_q - z_{s-1})),
 // and segments compose associatively:  (A1,F1,G1).(A2,F2,G2) = (A1 A2, A2 F1 + F2, G1 + A1 G2).
 //
 // Three kernels, reduce-then-scan over tiles of kScanTile points:
-//   k_tiles<.., false>  per tile and mode: (A, F, G) of the tile       (reduce)
-//   k_carry             per mode: exclusive prefix of F and suffix of G over tiles
-//   k_tiles<.., true>   per tile: chunk -> wave -> tile scans, both sweeps with
-//                       the carries, mode reduction, scatter u[slot] = value
-// Inside a tile each thread owns kScanChunk consecutive points and runs the
-// recurrences sequentially; chunks are combined with wave shuffles and LDS.
+//   k_reduce   one wave per tile: the tile's (A, F, G) for every mode.  When the
+//              tile is short on the decay scale (|tau| times its half-width small)
+//              the sums come from mode-independent power moments of the strengths
+//              about the tile centre c:  sum_q b_q exp(+-tau (z_q - c)) =
+//              sum_m (+-tau)^m mu_m / m!,  mu_m = sum_q b_q (z_q - c)^m;
+//              otherwise from the recurrences themselves.
+//   k_carry    per mode: exclusive prefix of F and suffix of G over tiles.
+//   k_final    per tile: chunk -> wave -> tile scans of both recurrences with
+//              the carries, sweeps, mode reduction, scatter u[slot] = value.
 #include "fgt_internal.h"
 
 namespace fgt {
@@ -65,12 +69,12 @@ template <class T>
 __device__ __forceinline__ T shfl_up(T v, int o) { return __shfl_up(v, (unsigned)o, kWave); }
 template <class T>
 __device__ __forceinline__ T shfl_down(T v, int o) { return __shfl_down(v, (unsigned)o, kWave); }
+template <class T>
+__device__ __forceinline__ T shfl_xor(T v, int o) { return __shfl_xor(v, o, kWave); }
 
-// Number of Taylor terms that make the truncation error of exp on
-// |w| <= kFastR fall below the type's rounding unit.
-template <class T> struct Taylor;
-template <> struct Taylor<double> { static constexpr int kDegree = 8; };   // (1/16)^9/9! = 4e-17
-template <> struct Taylor<float> { static constexpr int kDegree = 5; };    // (1/16)^6/6! = 8e-11
+template <class T> struct Prec;
+template <> struct Prec<double> { static constexpr double kUnit = 1.1102230246251565e-16; };  // 2^-53
+template <> struct Prec<float> { static constexpr double kUnit = 5.9604644775390625e-08; };    // 2^-24
 
 template <class T>
 __device__ __forceinline__ T exp_t(T v);
@@ -85,80 +89,279 @@ __device__ __forceinline__ void sincos_t(double v, double* s, double* c) { sinco
 template <>
 __device__ __forceinline__ void sincos_t(float v, float* s, float* c) { sincosf(v, s, c); }
 
-// Per-mode constants held uniformly by the whole block.
+// exp(-tau x) through the library exp and sincos; kept out of line so the
+// rare large-argument case does not cost registers in the hot loops.
 template <class T>
-struct ModeConst {
-  C<T> coef[Taylor<T>::kDegree + 1];  // (-tau)^m / m!
-  T tau_re, tau_im, om_re, om_im, dz_fast;
-};
-
-template <class T>
-__device__ __forceinline__ ModeConst<T> mode_const(const Modes& md, int k) {
-  ModeConst<T> mc;
-  const double tr = md.tau_re[k], ti = md.tau_im[k];
-  double cr = 1.0, ci = 0.0;
-  mc.coef[0] = {T(1), T(0)};
-#pragma unroll
-  for (int m = 1; m <= Taylor<T>::kDegree; ++m) {
-    // c_m = c_{m-1} * (-tau) / m
-    const double nr = (-tr * cr + ti * ci) / m;
-    const double ni = (-tr * ci - ti * cr) / m;
-    cr = nr;
-    ci = ni;
-    mc.coef[m] = {T(cr), T(ci)};
-  }
-  mc.tau_re = T(tr);
-  mc.tau_im = T(ti);
-  mc.om_re = T(md.om_re[k]);
-  mc.om_im = T(md.om_im[k]);
-  mc.dz_fast = T(md.dz_fast[k]);
-  return mc;
-}
-
-// e = exp(-tau dz) for dz >= 0.  Small arguments (|tau dz| <= kFastR, the
-// usual case: consecutive sorted points are close on the scale sqrt(delta))
-// use the Taylor polynomial in the real variable dz with complex
-// coefficients; larger ones the library exp and sincos.
-template <class T>
-__device__ __forceinline__ C<T> exp_neg(const ModeConst<T>& mc, T dz) {
-  if (dz <= mc.dz_fast) {
-    constexpr int D = Taylor<T>::kDegree;
-    C<T> p = mc.coef[D];
-#pragma unroll
-    for (int m = D - 1; m >= 0; --m) {
-      p.re = fma(p.re, dz, mc.coef[m].re);
-      p.im = fma(p.im, dz, mc.coef[m].im);
-    }
-    return p;
-  }
-  const T mag = exp_t(-mc.tau_re * dz);
+__device__ __noinline__ C<T> exp_neg_general(T tr, T ti, T x) {
+  const T mag = exp_t(-tr * x);
   T s, c;
-  sincos_t(mc.tau_im * dz, &s, &c);
+  sincos_t(ti * x, &s, &c);
   return {mag * c, -mag * s};
 }
 
+// 1/m! for the moment sums.
+struct InvFact {
+  double v[kMomentMax + 1];
+  constexpr InvFact() : v() {
+    double f = 1.0;
+    for (int m = 0; m <= kMomentMax; ++m) {
+      if (m > 0) f *= m;
+      v[m] = 1.0 / f;
+    }
+  }
+};
+__constant__ constexpr InvFact kInvFact{};
+
+template <class T>
+__device__ __forceinline__ T key_value(const void* keys, int64_t p) {
+  using K = typename KeyOf<T>::type;
+  return from_key(((const K*)keys)[p]);
+}
+
+// ---------------------------------------------------------------------------
+// k_reduce: (A, F, G) of every tile and mode.  One wave per tile.
+// ---------------------------------------------------------------------------
+template <class T, int NM>
+__global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void* keys1,
+                                                  const PassInfo* __restrict__ pass,
+                                                  const T* __restrict__ bs, int64_t P, Modes md,
+                                                  T* __restrict__ agg) {
+  const void* keys = pass->final_buf ? keys1 : keys0;
+  const int lane = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t t0 = tile * kScanTile;
+  const int n = (int)((P - t0) < kScanTile ? (P - t0) : kScanTile);
+  const T zfirst = key_value<T>(keys, t0);
+  const T zprev = t0 > 0 ? key_value<T>(keys, t0 - 1) : zfirst;
+  const T zlast = key_value<T>(keys, t0 + n - 1);
+  // Centre c and the exact distances to the tile's outer reference points.
+  const T c = zprev + (zlast - zprev) * T(0.5);
+  const T hf = zlast - c;
+  const T hg = c - zprev;
+  const T span = zlast - zprev;
+  const T r = T(md.tau_abs_max) * (hf > hg ? hf : hg);
+
+  // Number of moments: the series tail r^{K+1}/(K+1)! e^r must be below the unit roundoff.
+  int K = 0;
+  {
+    const T er = exp_t(r);
+    T t = r;
+    while (t * er > T(Prec<T>::kUnit) && K < kMomentMax) {
+      ++K;
+      t *= r / T(K + 1);
+    }
+    if (t * er > T(Prec<T>::kUnit)) K = -1;   // too wide: use the recurrences
+  }
+
+  if (K >= 0) {
+    T mu[kMomentMax + 1];
+#pragma unroll
+    for (int m = 0; m <= kMomentMax; ++m) mu[m] = T(0);
+    for (int e = lane; e < n; e += kWave) {
+      const T s = key_value<T>(keys, t0 + e) - c;
+      T pw = bs[t0 + e];
+      mu[0] += pw;
+#pragma unroll
+      for (int m = 1; m <= kMomentMax; ++m) {
+        if (m <= K) {
+          pw *= s;
+          mu[m] += pw;
+        }
+      }
+    }
+    // Butterfly sums: every lane ends with the same, order-fixed totals.
+#pragma unroll
+    for (int m = 0; m <= kMomentMax; ++m) {
+      if (m <= K) {
+#pragma unroll
+        for (int o = kWave / 2; o >= 1; o >>= 1) mu[m] += shfl_xor(mu[m], o);
+      }
+    }
+    if (lane < NM) {
+      const int k = lane;
+      const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
+      T top = T(0);
+#pragma unroll
+      for (int m = 0; m <= kMomentMax; ++m)
+        if (m == K) top = mu[m];
+      C<T> fs = {top * T(kInvFact.v[K]), T(0)};
+      C<T> gs = fs;
+#pragma unroll
+      for (int m = kMomentMax - 1; m >= 0; --m) {
+        if (m < K) {
+          const C<T> cm = {mu[m] * T(kInvFact.v[m]), T(0)};
+          fs = cfma(fs, C<T>{tr, ti}, cm);      // sum (tau)^m mu_m / m!
+          gs = cfma(gs, C<T>{-tr, -ti}, cm);    // sum (-tau)^m mu_m / m!
+        }
+      }
+      const C<T> ef = exp_neg_general<T>(tr, ti, hf);
+      const C<T> eg = exp_neg_general<T>(tr, ti, hg);
+      const C<T> a = exp_neg_general<T>(tr, ti, span);
+      const C<T> f = cmul(ef, fs);
+      const C<T> g = cmul(eg, gs);
+      T* o = agg + ((size_t)tile * NM + k) * 6;
+      o[0] = a.re; o[1] = a.im;
+      o[2] = f.re; o[3] = f.im;
+      o[4] = g.re; o[5] = g.im;
+    }
+    return;
+  }
+
+  // Wide tile: fold the recurrences over kPer consecutive points per lane,
+  // then compose the lanes' maps in order.
+  constexpr int kPer = kScanTile / kWave;
+  const int e0 = lane * kPer;
+  const int cnt = n - e0 < 0 ? 0 : (n - e0 < kPer ? n - e0 : kPer);
+#pragma unroll 1
+  for (int k = 0; k < NM; ++k) {
+    const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
+    Seg<T> s = seg_identity<T>();
+    // forward map (A, F)
+    T zl = e0 == 0 ? zprev : (cnt > 0 ? key_value<T>(keys, t0 + e0 - 1) : zlast);
+    for (int j = 0; j < cnt; ++j) {
+      const T zj = key_value<T>(keys, t0 + e0 + j);
+      const C<T> ex = exp_neg_general<T>(tr, ti, zj - zl);
+      s.a = cmul(s.a, ex);
+      s.f = cfma(ex, s.f, C<T>{bs[t0 + e0 + j], T(0)});
+      zl = zj;
+    }
+    // backward map G, last point first
+    C<T> g = {T(0), T(0)};
+    for (int j = cnt - 1; j >= 0; --j) {
+      const T zj = key_value<T>(keys, t0 + e0 + j);
+      const T zb = (e0 + j == 0) ? zprev : key_value<T>(keys, t0 + e0 + j - 1);
+      const C<T> ex = exp_neg_general<T>(tr, ti, zj - zb);
+      g = cmul(ex, cadd(g, C<T>{bs[t0 + e0 + j], T(0)}));
+    }
+    s.g = g;
+    Seg<T> pf = s, sb = s;
+    for (int o = 1; o < kWave; o <<= 1) {
+      Seg<T> l, rr;
+      l.a.re = shfl_up(pf.a.re, o); l.a.im = shfl_up(pf.a.im, o);
+      l.f.re = shfl_up(pf.f.re, o); l.f.im = shfl_up(pf.f.im, o);
+      if (lane >= o) {
+        pf.f = cfma(pf.a, l.f, pf.f);
+        pf.a = cmul(l.a, pf.a);
+      }
+      rr.a.re = shfl_down(sb.a.re, o); rr.a.im = shfl_down(sb.a.im, o);
+      rr.g.re = shfl_down(sb.g.re, o); rr.g.im = shfl_down(sb.g.im, o);
+      if (lane + o < kWave) {
+        sb.g = cfma(sb.a, rr.g, sb.g);
+        sb.a = cmul(sb.a, rr.a);
+      }
+    }
+    T* o = agg + ((size_t)tile * NM + k) * 6;
+    if (lane == kWave - 1) {
+      o[0] = pf.a.re; o[1] = pf.a.im;
+      o[2] = pf.f.re; o[3] = pf.f.im;
+    }
+    if (lane == 0) {
+      o[4] = sb.g.re; o[5] = sb.g.im;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_carry: carries over tiles for mode blockIdx.x.  CF[t] = forward value
+// entering tile t from the left (h+ at the point before it), CB[t] =
+// backward value entering from the right (h- at its last point).
+// ---------------------------------------------------------------------------
+template <class T, int NM>
+__global__ __launch_bounds__(kCarryThreads) void k_carry(const T* __restrict__ agg, int64_t tiles,
+                                                         T* __restrict__ carry) {
+  constexpr int W = kCarryThreads / kWave;
+  __shared__ Seg<T> wf[W], wb[W];
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave;
+  const int wave = tid / kWave;
+  const int64_t per = (tiles + kCarryThreads - 1) / kCarryThreads;
+  const int64_t a0 = (int64_t)tid * per;
+  const int64_t a1 = a0 + per < tiles ? a0 + per : tiles;
+
+  auto tile_seg = [&](int64_t t) {
+    const T* p = agg + ((size_t)t * NM + k) * 6;
+    Seg<T> s;
+    s.a = {p[0], p[1]};
+    s.f = {p[2], p[3]};
+    s.g = {p[4], p[5]};
+    return s;
+  };
+  Seg<T> mine = seg_identity<T>();
+#pragma unroll 8
+  for (int64_t t = a0; t < a1; ++t) mine = compose(mine, tile_seg(t));
+
+  Seg<T> pf = mine, sb = mine;
+  for (int o = 1; o < kWave; o <<= 1) {
+    Seg<T> l, r;
+    l.a.re = shfl_up(pf.a.re, o); l.a.im = shfl_up(pf.a.im, o);
+    l.f.re = shfl_up(pf.f.re, o); l.f.im = shfl_up(pf.f.im, o);
+    if (lane >= o) {
+      pf.f = cfma(pf.a, l.f, pf.f);
+      pf.a = cmul(l.a, pf.a);
+    }
+    r.a.re = shfl_down(sb.a.re, o); r.a.im = shfl_down(sb.a.im, o);
+    r.g.re = shfl_down(sb.g.re, o); r.g.im = shfl_down(sb.g.im, o);
+    if (lane + o < kWave) {
+      sb.g = cfma(sb.a, r.g, sb.g);
+      sb.a = cmul(sb.a, r.a);
+    }
+  }
+  if (lane == kWave - 1) wf[wave] = pf;
+  if (lane == 0) wb[wave] = sb;
+  __syncthreads();
+
+  C<T> cf = {T(0), T(0)};
+  C<T> cb = {T(0), T(0)};
+  for (int w = 0; w < wave; ++w) cf = cfma(wf[w].a, cf, wf[w].f);
+  for (int w = W - 1; w > wave; --w) cb = cfma(wb[w].a, cb, wb[w].g);
+  Seg<T> xl, xr;
+  xl.a.re = shfl_up(pf.a.re, 1); xl.a.im = shfl_up(pf.a.im, 1);
+  xl.f.re = shfl_up(pf.f.re, 1); xl.f.im = shfl_up(pf.f.im, 1);
+  xr.a.re = shfl_down(sb.a.re, 1); xr.a.im = shfl_down(sb.a.im, 1);
+  xr.g.re = shfl_down(sb.g.re, 1); xr.g.im = shfl_down(sb.g.im, 1);
+  if (lane > 0) cf = cfma(xl.a, cf, xl.f);
+  if (lane < kWave - 1) cb = cfma(xr.a, cb, xr.g);
+
+#pragma unroll 8
+  for (int64_t t = a0; t < a1; ++t) {
+    T* o = carry + ((size_t)t * NM + k) * 4;
+    o[0] = cf.re;
+    o[1] = cf.im;
+    const Seg<T> s = tile_seg(t);
+    cf = cfma(s.a, cf, s.f);
+  }
+#pragma unroll 8
+  for (int64_t t = a1 - 1; t >= a0; --t) {
+    T* o = carry + ((size_t)t * NM + k) * 4;
+    o[2] = cb.re;
+    o[3] = cb.im;
+    const Seg<T> s = tile_seg(t);
+    cb = cfma(s.a, cb, s.g);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_final: both sweeps with the carries, mode reduction, scatter.
+// ---------------------------------------------------------------------------
 template <class T>
 struct Staged {
   T z[kScanTile + kScanTile / kScanChunk];
   T b[kScanTile + kScanTile / kScanChunk];
-  uint32_t slot[kScanTile + kScanTile / kScanChunk];   // output index; kNoSlot for a source
+  uint32_t slot[kScanTile + kScanTile / kScanChunk];
 };
 
 __device__ __forceinline__ int lds_pos(int e) { return e + e / kScanChunk; }
-constexpr uint32_t kNoSlot = 0xffffffffu;
 
-// Tile kernel.  FINAL = false: write the tile's (A, F, G) per mode.
-// FINAL = true: read the tile's carries, run both sweeps, write u.
-template <class T, int NM, bool FINAL>
-__global__ __launch_bounds__(kScanThreads) void k_tiles(
-    const void* keys0, const void* keys1, const uint32_t* idx0, const uint32_t* idx1,
-    const PassInfo* __restrict__ pass, const T* __restrict__ alpha, int64_t N, int64_t P, Modes md,
-    T* __restrict__ agg, const T* __restrict__ carry, T* __restrict__ u) {
-  using K = typename KeyOf<T>::type;
-  // The sorted keys sit in whichever buffer the last radix pass wrote.
-  const int fb = pass->final_buf;
-  const K* __restrict__ keys = (const K*)(fb ? keys1 : keys0);
-  const uint32_t* __restrict__ idx = fb ? idx1 : idx0;
+template <class T, int NM>
+__global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const void* keys1,
+                                                        const PassInfo* __restrict__ pass,
+                                                        const T* __restrict__ bs,
+                                                        const uint32_t* __restrict__ slots,
+                                                        int64_t M, int64_t P, Modes md,
+                                                        const T* __restrict__ carry,
+                                                        T* __restrict__ u) {
+  const void* keys = pass->final_buf ? keys1 : keys0;
   __shared__ Staged<T> st;
   __shared__ Seg<T> wtot[NM][kScanWaves][2];   // per wave: [0] forward total, [1] backward total
   const int tid = threadIdx.x;
@@ -167,18 +370,14 @@ __global__ __launch_bounds__(kScanThreads) void k_tiles(
   const int64_t tile = blockIdx.x;
   const int64_t t0 = tile * kScanTile;
 
-  // Stage the tile: coalesced reads of keys and payloads, gather alpha.
   for (int e = tid; e < kScanTile; e += kScanThreads) {
     const int64_t p = t0 + e;
     T z = T(0), b = T(0);
     uint32_t slot = kNoSlot;
     if (p < P) {
-      z = from_key(keys[p]);
-      const uint32_t id = idx[p];
-      if ((int64_t)id < N)
-        b = alpha[id];
-      else if ((int64_t)id < P)
-        slot = (uint32_t)((int64_t)id - N);
+      z = key_value<T>(keys, p);
+      b = bs[p];
+      slot = slots[p];
     }
     const int q = lds_pos(e);
     st.z[q] = z;
@@ -186,14 +385,15 @@ __global__ __launch_bounds__(kScanThreads) void k_tiles(
     st.slot[q] = slot;
   }
   T zprev = T(0);
-  if (tid == 0) zprev = t0 > 0 ? from_key(keys[t0 - 1]) : T(0);
+  if (tid == 0) zprev = t0 > 0 ? key_value<T>(keys, t0 - 1) : T(0);
   __syncthreads();
 
   // This thread's chunk: gaps dz_j = z_j - z_{j-1} and strengths b_j.
   const int e0 = tid * kScanChunk;
   T dz[kScanChunk], bb[kScanChunk];
+  T dzmax = T(0);
   {
-    const int64_t valid = P - t0;   // points of this tile that exist
+    const int64_t valid = P - t0;
     T zl;
     if (tid == 0)
       zl = t0 > 0 ? zprev : st.z[lds_pos(0)];
@@ -206,7 +406,14 @@ __global__ __launch_bounds__(kScanThreads) void k_tiles(
       dz[j] = (e < valid) ? zj - zl : T(0);
       bb[j] = st.b[lds_pos(e)];
       zl = (e < valid) ? zj : zl;
+      dzmax = dz[j] > dzmax ? dz[j] : dzmax;
     }
+  }
+  // Largest gap in the wave: sets the Taylor degree of the mode exponentials.
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) {
+    const T other = shfl_xor(dzmax, o);
+    dzmax = other > dzmax ? other : dzmax;
   }
 
   T acc[kScanChunk];
@@ -215,10 +422,47 @@ __global__ __launch_bounds__(kScanThreads) void k_tiles(
 
 #pragma unroll 1
   for (int k = 0; k < NM; ++k) {
-    const ModeConst<T> mc = mode_const<T>(md, k);
+    const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
+    const T om_re = T(md.om_re[k]), om_im = T(md.om_im[k]);
+    // Degree D: smallest with (|tau| dzmax)^{D+1}/(D+1)! below the unit roundoff.
+    const double rr = md.tau_abs[k] * (double)dzmax;
+    int D = kTaylorMax;
+#pragma unroll
+    for (int d = kTaylorMax; d >= 1; --d)
+      if (rr <= md.taylor_thr[d]) D = d;
+    const T dz_lim = T(md.taylor_thr[kTaylorMax] / md.tau_abs[k]);
+
+    // e_j = sum_{m<=D} (-tau)^m dz_j^m / m!  (Horner in the real variable dz)
     C<T> ex[kScanChunk];
 #pragma unroll
-    for (int j = 0; j < kScanChunk; ++j) ex[j] = exp_neg(mc, dz[j]);
+    for (int j = 0; j < kScanChunk; ++j) ex[j] = {T(0), T(0)};
+    {
+      double cr = 1.0, ci = 0.0;   // (-tau)^m / m!, m = 0..kTaylorMax
+      double coef_re[kTaylorMax + 1], coef_im[kTaylorMax + 1];
+#pragma unroll
+      for (int m = 0; m <= kTaylorMax; ++m) {
+        coef_re[m] = cr;
+        coef_im[m] = ci;
+        const double nr = (-md.tau_re[k] * cr + md.tau_im[k] * ci) / (m + 1);
+        const double ni = (-md.tau_re[k] * ci - md.tau_im[k] * cr) / (m + 1);
+        cr = nr;
+        ci = ni;
+      }
+#pragma unroll
+      for (int m = kTaylorMax; m >= 0; --m) {
+        if (m <= D) {
+          const T c_re = T(coef_re[m]), c_im = T(coef_im[m]);
+#pragma unroll
+          for (int j = 0; j < kScanChunk; ++j) {
+            ex[j].re = fma(ex[j].re, dz[j], c_re);
+            ex[j].im = fma(ex[j].im, dz[j], c_im);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j)
+      if (dz[j] > dz_lim) ex[j] = exp_neg_general<T>(tr, ti, dz[j]);
 
     // Chunk map.
     Seg<T> s;
@@ -256,138 +500,40 @@ __global__ __launch_bounds__(kScanThreads) void k_tiles(
     if (lane == 0) wtot[k][wave][1] = sb;
     __syncthreads();
 
-    // Tile totals (reduce) or carries into this chunk (final).
-    if (!FINAL) {
-      if (tid == 0) {
-        Seg<T> tot = seg_identity<T>();
-        Seg<T> totb = seg_identity<T>();
-        for (int w = 0; w < kScanWaves; ++w) {
-          const Seg<T> fw = wtot[k][w][0];
-          const Seg<T> bw = wtot[k][w][1];
-          tot.f = cfma(fw.a, tot.f, fw.f);
-          tot.a = cmul(tot.a, fw.a);
-          totb.g = cfma(totb.a, bw.g, totb.g);
-          totb.a = cmul(totb.a, bw.a);
-        }
-        T* o = agg + ((size_t)tile * NM + k) * 6;
-        o[0] = tot.a.re; o[1] = tot.a.im;
-        o[2] = tot.f.re; o[3] = tot.f.im;
-        o[4] = totb.g.re; o[5] = totb.g.im;
-      }
-    } else {
-      const T* cr = carry + ((size_t)tile * NM + k) * 4;
-      C<T> cf = {cr[0], cr[1]};
-      C<T> cb = {cr[2], cr[3]};
-      for (int w = 0; w < wave; ++w) cf = cfma(wtot[k][w][0].a, cf, wtot[k][w][0].f);
-      for (int w = kScanWaves - 1; w > wave; --w) cb = cfma(wtot[k][w][1].a, cb, wtot[k][w][1].g);
-      // exclusive lane prefix / suffix
-      Seg<T> xl, xr;
-      xl.a.re = shfl_up(pf.a.re, 1); xl.a.im = shfl_up(pf.a.im, 1);
-      xl.f.re = shfl_up(pf.f.re, 1); xl.f.im = shfl_up(pf.f.im, 1);
-      xr.a.re = shfl_down(sb.a.re, 1); xr.a.im = shfl_down(sb.a.im, 1);
-      xr.g.re = shfl_down(sb.g.re, 1); xr.g.im = shfl_down(sb.g.im, 1);
-      if (lane > 0) cf = cfma(xl.a, cf, xl.f);
-      if (lane < kWave - 1) cb = cfma(xr.a, cb, xr.g);
+    const T* cr = carry + ((size_t)tile * NM + k) * 4;
+    C<T> cf = {cr[0], cr[1]};
+    C<T> cb = {cr[2], cr[3]};
+    for (int w = 0; w < wave; ++w) cf = cfma(wtot[k][w][0].a, cf, wtot[k][w][0].f);
+    for (int w = kScanWaves - 1; w > wave; --w) cb = cfma(wtot[k][w][1].a, cb, wtot[k][w][1].g);
+    // exclusive lane prefix / suffix
+    Seg<T> xl, xr;
+    xl.a.re = shfl_up(pf.a.re, 1); xl.a.im = shfl_up(pf.a.im, 1);
+    xl.f.re = shfl_up(pf.f.re, 1); xl.f.im = shfl_up(pf.f.im, 1);
+    xr.a.re = shfl_down(sb.a.re, 1); xr.a.im = shfl_down(sb.a.im, 1);
+    xr.g.re = shfl_down(sb.g.re, 1); xr.g.im = shfl_down(sb.g.im, 1);
+    if (lane > 0) cf = cfma(xl.a, cf, xl.f);
+    if (lane < kWave - 1) cb = cfma(xr.a, cb, xr.g);
 
-      // Forward sweep: h+ at every point of the chunk.
-      C<T> h = cf;
-#pragma unroll
-      for (int j = 0; j < kScanChunk; ++j) {
-        h = cfma(ex[j], h, C<T>{bb[j], T(0)});
-        acc[j] = fma(mc.om_re, h.re, fma(-mc.om_im, h.im, acc[j]));
-      }
-      // Backward sweep: h- (exclusive) at every point.
-      C<T> g = cb;
-#pragma unroll
-      for (int j = kScanChunk - 1; j >= 0; --j) {
-        acc[j] = fma(mc.om_re, g.re, fma(-mc.om_im, g.im, acc[j]));
-        g = cmul(ex[j], cadd(g, C<T>{bb[j], T(0)}));
-      }
-    }
-  }
-
-  if (FINAL) {
+    // Forward sweep: h+ at every point of the chunk.
+    C<T> h = cf;
 #pragma unroll
     for (int j = 0; j < kScanChunk; ++j) {
-      const uint32_t slot = st.slot[lds_pos(e0 + j)];
-      if ((int64_t)slot < P - N) u[slot] = acc[j];
+      h = cfma(ex[j], h, C<T>{bb[j], T(0)});
+      acc[j] = fma(om_re, h.re, fma(-om_im, h.im, acc[j]));
+    }
+    // Backward sweep: h- (exclusive) at every point.
+    C<T> g = cb;
+#pragma unroll
+    for (int j = kScanChunk - 1; j >= 0; --j) {
+      acc[j] = fma(om_re, g.re, fma(-om_im, g.im, acc[j]));
+      g = cmul(ex[j], cadd(g, C<T>{bb[j], T(0)}));
     }
   }
-}
 
-// Carries over tiles for mode blockIdx.x: CF[t] = forward value entering tile
-// t from the left (h+ at the point before it), CB[t] = backward value
-// entering from the right (h- at its last point).
-template <class T, int NM>
-__global__ __launch_bounds__(kCarryThreads) void k_carry(const T* __restrict__ agg, int64_t tiles,
-                                                         T* __restrict__ carry) {
-  constexpr int W = kCarryThreads / kWave;
-  __shared__ Seg<T> wf[W], wb[W];
-  const int k = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int lane = tid % kWave;
-  const int wave = tid / kWave;
-  const int64_t per = (tiles + kCarryThreads - 1) / kCarryThreads;
-  const int64_t a0 = (int64_t)tid * per;
-  const int64_t a1 = a0 + per < tiles ? a0 + per : tiles;
-
-  auto tile_seg = [&](int64_t t) {
-    const T* p = agg + ((size_t)t * NM + k) * 6;
-    Seg<T> s;
-    s.a = {p[0], p[1]};
-    s.f = {p[2], p[3]};
-    s.g = {p[4], p[5]};
-    return s;
-  };
-  // Fold this thread's tiles.
-  Seg<T> mine = seg_identity<T>();
-  for (int64_t t = a0; t < a1; ++t) mine = compose(mine, tile_seg(t));
-
-  Seg<T> pf = mine, sb = mine;
-  for (int o = 1; o < kWave; o <<= 1) {
-    Seg<T> l, r;
-    l.a.re = shfl_up(pf.a.re, o); l.a.im = shfl_up(pf.a.im, o);
-    l.f.re = shfl_up(pf.f.re, o); l.f.im = shfl_up(pf.f.im, o);
-    if (lane >= o) {
-      pf.f = cfma(pf.a, l.f, pf.f);
-      pf.a = cmul(l.a, pf.a);
-    }
-    r.a.re = shfl_down(sb.a.re, o); r.a.im = shfl_down(sb.a.im, o);
-    r.g.re = shfl_down(sb.g.re, o); r.g.im = shfl_down(sb.g.im, o);
-    if (lane + o < kWave) {
-      sb.g = cfma(sb.a, r.g, sb.g);
-      sb.a = cmul(sb.a, r.a);
-    }
-  }
-  if (lane == kWave - 1) wf[wave] = pf;
-  if (lane == 0) wb[wave] = sb;
-  __syncthreads();
-
-  C<T> cf = {T(0), T(0)};
-  C<T> cb = {T(0), T(0)};
-  for (int w = 0; w < wave; ++w) cf = cfma(wf[w].a, cf, wf[w].f);
-  for (int w = W - 1; w > wave; --w) cb = cfma(wb[w].a, cb, wb[w].g);
-  Seg<T> xl, xr;
-  xl.a.re = shfl_up(pf.a.re, 1); xl.a.im = shfl_up(pf.a.im, 1);
-  xl.f.re = shfl_up(pf.f.re, 1); xl.f.im = shfl_up(pf.f.im, 1);
-  xr.a.re = shfl_down(sb.a.re, 1); xr.a.im = shfl_down(sb.a.im, 1);
-  xr.g.re = shfl_down(sb.g.re, 1); xr.g.im = shfl_down(sb.g.im, 1);
-  if (lane > 0) cf = cfma(xl.a, cf, xl.f);
-  if (lane < kWave - 1) cb = cfma(xr.a, cb, xr.g);
-
-  for (int64_t t = a0; t < a1; ++t) {
-    T* o = carry + ((size_t)t * NM + k) * 4;
-    o[0] = cf.re;
-    o[1] = cf.im;
-    const Seg<T> s = tile_seg(t);
-    cf = cfma(s.a, cf, s.f);
-  }
-  for (int64_t t = a1 - 1; t >= a0; --t) {
-    T* o = carry + ((size_t)t * NM + k) * 4;
-    o[2] = cb.re;
-    o[3] = cb.im;
-    const Seg<T> s = tile_seg(t);
-    cb = cfma(s.a, cb, s.g);
+#pragma unroll
+  for (int j = 0; j < kScanChunk; ++j) {
+    const uint32_t slot = st.slot[lds_pos(e0 + j)];
+    if ((int64_t)slot < M) u[slot] = acc[j];
   }
 }
 
@@ -399,18 +545,18 @@ __global__ void k_fill_zero(T* __restrict__ u, int64_t n) {
 }
 
 template <class T, int NM>
-hipError_t scan_nm(const Workspace& w, const Modes& md, const T* alpha, int64_t M, int64_t N, T* u,
-                   hipStream_t s, Timeline* tl) {
+hipError_t scan_nm(const Workspace& w, const Modes& md, int64_t M, int64_t N, T* u, hipStream_t s,
+                   Timeline* tl) {
   const int64_t P = M + N;
   const dim3 grid((unsigned)w.scan_tiles);
-  hipLaunchKernelGGL((k_tiles<T, NM, false>), grid, dim3(kScanThreads), 0, s, w.keys[0], w.keys[1],
-                     w.idx[0], w.idx[1], w.pass, alpha, N, P, md, (T*)w.agg, (const T*)w.carry, u);
+  hipLaunchKernelGGL((k_reduce<T, NM>), grid, dim3(kWave), 0, s, w.keys[0], w.keys[1], w.pass,
+                     (const T*)w.b, P, md, (T*)w.agg);
   tl->mark(s);
   hipLaunchKernelGGL((k_carry<T, NM>), dim3(NM), dim3(kCarryThreads), 0, s, (const T*)w.agg,
                      w.scan_tiles, (T*)w.carry);
   tl->mark(s);
-  hipLaunchKernelGGL((k_tiles<T, NM, true>), grid, dim3(kScanThreads), 0, s, w.keys[0], w.keys[1],
-                     w.idx[0], w.idx[1], w.pass, alpha, N, P, md, (T*)w.agg, (const T*)w.carry, u);
+  hipLaunchKernelGGL((k_final<T, NM>), grid, dim3(kScanThreads), 0, s, w.keys[0], w.keys[1], w.pass,
+                     (const T*)w.b, w.slot, M, P, md, (const T*)w.carry, u);
   tl->mark(s);
   return hipGetLastError();
 }
@@ -418,17 +564,17 @@ hipError_t scan_nm(const Workspace& w, const Modes& md, const T* alpha, int64_t 
 }  // namespace
 
 template <class T>
-hipError_t scan_points(const Workspace& w, const Modes& md, const T* alpha, int64_t M, int64_t N,
-                       T* u, hipStream_t s, Timeline* tl) {
+hipError_t scan_points(const Workspace& w, const Modes& md, int64_t M, int64_t N, T* u,
+                       hipStream_t s, Timeline* tl) {
   switch (md.n) {
-    case 1: return scan_nm<T, 1>(w, md, alpha, M, N, u, s, tl);
-    case 2: return scan_nm<T, 2>(w, md, alpha, M, N, u, s, tl);
-    case 3: return scan_nm<T, 3>(w, md, alpha, M, N, u, s, tl);
-    case 4: return scan_nm<T, 4>(w, md, alpha, M, N, u, s, tl);
-    case 5: return scan_nm<T, 5>(w, md, alpha, M, N, u, s, tl);
-    case 6: return scan_nm<T, 6>(w, md, alpha, M, N, u, s, tl);
-    case 7: return scan_nm<T, 7>(w, md, alpha, M, N, u, s, tl);
-    case 8: return scan_nm<T, 8>(w, md, alpha, M, N, u, s, tl);
+    case 1: return scan_nm<T, 1>(w, md, M, N, u, s, tl);
+    case 2: return scan_nm<T, 2>(w, md, M, N, u, s, tl);
+    case 3: return scan_nm<T, 3>(w, md, M, N, u, s, tl);
+    case 4: return scan_nm<T, 4>(w, md, M, N, u, s, tl);
+    case 5: return scan_nm<T, 5>(w, md, M, N, u, s, tl);
+    case 6: return scan_nm<T, 6>(w, md, M, N, u, s, tl);
+    case 7: return scan_nm<T, 7>(w, md, M, N, u, s, tl);
+    case 8: return scan_nm<T, 8>(w, md, M, N, u, s, tl);
     default: return hipErrorInvalidValue;
   }
 }
@@ -442,10 +588,10 @@ hipError_t fill_zero(T* u, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-template hipError_t scan_points<double>(const Workspace&, const Modes&, const double*, int64_t,
-                                        int64_t, double*, hipStream_t, Timeline*);
-template hipError_t scan_points<float>(const Workspace&, const Modes&, const float*, int64_t,
-                                       int64_t, float*, hipStream_t, Timeline*);
+template hipError_t scan_points<double>(const Workspace&, const Modes&, int64_t, int64_t, double*,
+                                        hipStream_t, Timeline*);
+template hipError_t scan_points<float>(const Workspace&, const Modes&, int64_t, int64_t, float*,
+                                       hipStream_t, Timeline*);
 template hipError_t fill_zero<double>(double*, int64_t, hipStream_t);
 template hipError_t fill_zero<float>(float*, int64_t, hipStream_t);
 

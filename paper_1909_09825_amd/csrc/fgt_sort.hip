@@ -29,6 +29,7 @@ constexpr int kRaw = 2;
 // A look-back wait longer than this means a predecessor tile never published;
 // the pass then stops waiting and raises kStatusInternal instead of hanging.
 constexpr uint32_t kSpinLimit = 1u << 24;
+constexpr int kLookWindow = 8;
 
 __global__ void k_clear(uint32_t* __restrict__ p, size_t n_words) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -46,7 +47,8 @@ template <class T>
 __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, const T* __restrict__ y,
                                                    int64_t N, int64_t P,
                                                    uint32_t* __restrict__ hist,
-                                                   uint32_t* __restrict__ status) {
+                                                   uint32_t* __restrict__ status,
+                                                   unsigned long long* __restrict__ maxabs) {
   using K = typename KeyOf<T>::type;
   constexpr int D = KeyOf<T>::kDigits;
   __shared__ uint32_t h[D * kRadix];
@@ -59,10 +61,12 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
 #pragma unroll
   for (int d = 0; d < D; ++d) { cur[d] = 0u; cnt[d] = 0u; }
   bool bad = false;
+  T zmax = T(0);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += stride) {
     const T z = load_point(x, y, N, p);
     bad |= !isfinite(z);
+    zmax = fabs(z) > zmax ? fabs(z) : zmax;
     const K k = to_key(z);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -79,6 +83,14 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
   for (int d = 0; d < D; ++d)
     if (cnt[d]) atomicAdd(&h[d * kRadix + cur[d]], cnt[d]);
   if (bad) atomicOr(status, kStatusNonFinite);
+  // Non-negative floats order like their bit patterns.
+  unsigned long long zbits = sizeof(T) == 8 ? (unsigned long long)__double_as_longlong((double)zmax)
+                                            : (unsigned long long)__float_as_uint((float)zmax);
+  for (int o = kWave / 2; o >= 1; o >>= 1) {
+    const unsigned long long other = __shfl_xor(zbits, o, kWave);
+    zbits = other > zbits ? other : zbits;
+  }
+  if ((threadIdx.x % kWave) == 0) atomicMax(maxabs, zbits);
   __syncthreads();
   for (int i = threadIdx.x; i < D * kRadix; i += blockDim.x)
     if (h[i]) atomicAdd(&hist[i], h[i]);
@@ -87,7 +99,8 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
 // One block of 256 threads (one per digit value).
 template <class T>
 __global__ __launch_bounds__(256) void k_plan(const uint32_t* __restrict__ hist, int64_t P,
-                                              uint32_t* __restrict__ dig_off,
+                                              const unsigned long long* __restrict__ maxabs,
+                                              double key_width, uint32_t* __restrict__ dig_off,
                                               PassInfo* __restrict__ pass) {
   constexpr int D = KeyOf<T>::kDigits;
   __shared__ uint32_t scan[kRadix];
@@ -111,9 +124,33 @@ __global__ __launch_bounds__(256) void k_plan(const uint32_t* __restrict__ hist,
     __syncthreads();
   }
   if (b == 0) {
+    // Low digits below the key resolution: the largest |z| has the largest
+    // spacing between neighbouring floats, ulp; keys that agree above digit k
+    // differ by less than 256^k ulp.
+    int skip = 0;
+    {
+      const unsigned long long zb = *maxabs;
+      double ulp;
+      if (sizeof(T) == 8) {
+        const int ex = (int)((zb >> 52) & 0x7ff);
+        ulp = ex == 0x7ff ? INFINITY : ldexp(1.0, (ex == 0 ? 1 : ex) - 1075);
+      } else {
+        const int ex = (int)((zb >> 23) & 0xff);
+        ulp = ex == 0xff ? INFINITY : ldexp(1.0, (ex == 0 ? 1 : ex) - 150);
+      }
+      if (key_width > 0.0 && ulp < INFINITY) {
+        double span = ulp;
+        while (skip < D - 1 && span * 256.0 <= key_width) {
+          span *= 256.0;
+          ++skip;
+        }
+      }
+    }
+    for (int d = 0; d < skip; ++d) trivial[d] = 1;
+    pass->skipped_low = skip;
     int any = 0;
     for (int d = 0; d < D; ++d) any |= !trivial[d];
-    int runs = 0, last_out = 0;
+    int runs = 0, last_out = 0, last_pass = 0;
     for (int d = 0; d < 8; ++d) {
       int run = (d < D) && !trivial[d];
       if (!any && d == D - 1) run = 1;  // all keys equal: one pass materialises them
@@ -121,19 +158,22 @@ __global__ __launch_bounds__(256) void k_plan(const uint32_t* __restrict__ hist,
       if (run) {
         pass->src[d] = runs == 0 ? kRaw : (runs - 1) % 2;
         last_out = runs % 2;
+        last_pass = d;
         ++runs;
       } else {
         pass->src[d] = -1;
       }
     }
     pass->final_buf = last_out;
+    pass->last_pass = last_pass;
   }
 }
 
 template <class T>
-__global__ __launch_bounds__(kSortThreads) void k_onesweep(
-    int d, const T* __restrict__ x, const T* __restrict__ y, int64_t N, int64_t P,
-    void* keys0, void* keys1, uint32_t* idx0, uint32_t* idx1,
+__global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
+    int d, const T* __restrict__ x, const T* __restrict__ y, const T* __restrict__ alpha, int64_t N,
+    int64_t P, void* keys0, void* keys1, uint32_t* idx0, uint32_t* idx1, T* __restrict__ b_out,
+    uint32_t* __restrict__ slot_out,
     const uint32_t* __restrict__ dig_off, const PassInfo* __restrict__ pass,
     uint32_t* __restrict__ tile_ctr, uint64_t* lb_cur, uint64_t* lb_next,
     uint32_t* __restrict__ status) {
@@ -141,8 +181,8 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(
   __shared__ uint32_t wcnt[kSortWaves][kRadix];   // per-wave running digit counts, then wave offsets
   __shared__ uint32_t tstart[kRadix];             // tile-local exclusive digit starts
   __shared__ uint64_t gbase[kRadix];              // global output position of each digit's run
-  __shared__ K skeys[kSortTile];
-  __shared__ uint32_t sidx[kSortTile];
+  __shared__ uint32_t wsum[kRadix / kWave];
+  __shared__ K stage[kSortTile];                  // keys, then (reused) payloads, in digit order
   __shared__ int s_tile;
 
   const int tid = threadIdx.x;
@@ -150,15 +190,17 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(
   const int src = pass->src[d];
   if (!run) {
     // Nothing moves; still clear the other look-back buffer for the next pass.
-    for (int64_t t = blockIdx.x; t * kSortTile < P; t += gridDim.x)
-      lb_next[(size_t)t * kRadix + tid] = 0ull;
+    if (tid < kRadix)
+      for (int64_t t = blockIdx.x; t * kSortTile < P; t += gridDim.x)
+        lb_next[(size_t)t * kRadix + tid] = 0ull;
     return;
   }
   if (tid == 0) s_tile = (int)atomicAdd(&tile_ctr[d], 1u);
-  for (int w = 0; w < kSortWaves; ++w) wcnt[w][tid] = 0u;
+  for (int i = tid; i < kSortWaves * kRadix; i += kSortThreads) (&wcnt[0][0])[i] = 0u;
   __syncthreads();
   const int tile = s_tile;
-  lb_next[(size_t)tile * kRadix + tid] = 0ull;
+  const bool digit_thread = tid < kRadix;   // threads 0..255 own one digit value each
+  if (digit_thread) lb_next[(size_t)tile * kRadix + tid] = 0ull;
 
   const K* kin = src == 1 ? (const K*)keys1 : (const K*)keys0;
   const uint32_t* iin = src == 1 ? idx1 : idx0;
@@ -218,7 +260,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(
 
   // Tile histogram, wave offsets, publish the tile's aggregate.
   uint32_t tcount = 0u;
-  {
+  if (digit_thread) {
     uint32_t run_sum = 0u;
 #pragma unroll
     for (int w = 0; w < kSortWaves; ++w) {
@@ -227,72 +269,120 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(
       run_sum += c;
     }
     tcount = run_sum;
+    __hip_atomic_store(&lb_cur[(size_t)tile * kRadix + tid], kFlagAgg | (uint64_t)tcount,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  __hip_atomic_store(&lb_cur[(size_t)tile * kRadix + tid], kFlagAgg | (uint64_t)tcount,
-                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
-  // Exclusive scan of the tile histogram over digits.
-  tstart[tid] = tcount;
-  __syncthreads();
-  for (int o = 1; o < kRadix; o <<= 1) {
-    const uint32_t v = tid >= o ? tstart[tid - o] : 0u;
-    __syncthreads();
-    tstart[tid] += v;
-    __syncthreads();
-  }
-  const uint32_t tincl = tstart[tid];
-  __syncthreads();
-  tstart[tid] = tincl - tcount;
-
-  // Decoupled look-back over earlier tiles for this digit.
-  uint64_t excl = 0ull;
-  uint32_t spins = 0u;
-  for (int j = tile - 1; j >= 0;) {
-    const uint64_t v = __hip_atomic_load(&lb_cur[(size_t)j * kRadix + tid], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t f = v & ~kValueMask;
-    if (f == 0ull) {
-      if (++spins > kSpinLimit) {
-        atomicOr(status, kStatusInternal);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    excl += v & kValueMask;
-    if (f == kFlagPrefix) break;
-    --j;
-  }
-  __hip_atomic_store(&lb_cur[(size_t)tile * kRadix + tid], kFlagPrefix | (excl + tcount),
-                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  gbase[tid] = (uint64_t)dig_off[d * kRadix + tid] + excl;
-  __syncthreads();
-
-  // Sort the tile by digit in LDS.
+  // Exclusive scan of the tile histogram over digits (thread tid owns digit tid).
+  {
+    uint32_t incl = tcount;
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    const int64_t p = base + i * kWave + lane;
-    if (p < P) {
-      const uint32_t dig = (uint32_t)(key[i] >> shift) & 0xffu;
-      const uint32_t pos = tstart[dig] + wcnt[wave][dig] + rank[i];
-      if (pos < (uint32_t)kSortTile) {
-        skeys[pos] = key[i];
-        sidx[pos] = id[i];
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, (unsigned)o, kWave);
+      if (lane >= o) incl += v;
+    }
+    if (digit_thread && lane == kWave - 1) wsum[wave] = incl;
+    __syncthreads();
+    if (digit_thread) {
+      uint32_t before = 0u;
+      for (int w = 0; w < wave; ++w) before += wsum[w];
+      tstart[tid] = before + incl - tcount;
+    }
+  }
+
+  // Decoupled look-back over earlier tiles for this digit, kLookWindow
+  // predecessors per round so their load latencies overlap.
+  if (digit_thread) {
+    uint64_t excl = 0ull;
+    uint32_t spins = 0u;
+    int j = tile - 1;
+    while (j >= 0) {
+      uint64_t v[kLookWindow];
+#pragma unroll
+      for (int q = 0; q < kLookWindow; ++q)
+        v[q] = (j - q >= 0) ? __hip_atomic_load(&lb_cur[(size_t)(j - q) * kRadix + tid],
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : kFlagPrefix;
+      int used = 0;
+      bool done = false;
+#pragma unroll
+      for (int q = 0; q < kLookWindow; ++q) {
+        if (!done && used == q) {
+          const uint64_t f = v[q] & ~kValueMask;
+          if (f != 0ull) {
+            excl += v[q] & kValueMask;
+            ++used;
+            done = f == kFlagPrefix;
+          }
+        }
+      }
+      j -= used;
+      if (done) break;
+      if (used == 0) {
+        if (++spins > kSpinLimit) {
+          atomicOr(status, kStatusInternal);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
     }
+    __hip_atomic_store(&lb_cur[(size_t)tile * kRadix + tid], kFlagPrefix | (excl + tcount),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    gbase[tid] = (uint64_t)dig_off[d * kRadix + tid] + excl;
   }
   __syncthreads();
 
-  // Write each digit's run to its global position.
+  // Sort the tile by digit in LDS (keys first, then payloads through the same
+  // buffer) and write each digit's run to its global position.
   const int64_t tile_begin = (int64_t)tile * kSortTile;
   const int nvalid = (int)((P - tile_begin) < kSortTile ? (P - tile_begin) : kSortTile);
-  for (int j = tid; j < nvalid; j += kSortThreads) {
-    const K k = skeys[j];
-    const uint32_t dig = (uint32_t)(k >> shift) & 0xffu;
-    const uint64_t out = gbase[dig] + (uint64_t)(j - (int)tstart[dig]);
-    if (out < (uint64_t)P) {
-      kout[out] = k;
-      iout[out] = sidx[j];
+  uint32_t pos[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const uint32_t dig = (uint32_t)(key[i] >> shift) & 0xffu;
+    pos[i] = tstart[dig] + wcnt[wave][dig] + rank[i];
+    if (base + i * kWave + lane < P && pos[i] < (uint32_t)kSortTile) stage[pos[i]] = key[i];
+  }
+  __syncthreads();
+  // Each thread visits the same positions j in both write loops; the output
+  // index found for the key is kept for the payload.
+  uint32_t outpos[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int j = tid + r * kSortThreads;
+    outpos[r] = 0xffffffffu;
+    if (j < nvalid) {
+      const K k = stage[j];
+      const uint32_t dig = (uint32_t)(k >> shift) & 0xffu;
+      const uint64_t out = gbase[dig] + (uint64_t)(j - (int)tstart[dig]);
+      if (out < (uint64_t)P) {
+        outpos[r] = (uint32_t)out;
+        kout[out] = k;
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t* sid = (uint32_t*)stage;
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i)
+    if (base + i * kWave + lane < P && pos[i] < (uint32_t)kSortTile) sid[pos[i]] = id[i];
+  __syncthreads();
+  // The last pass writes, instead of the permutation, what the scan needs:
+  // the strength of each sorted point (alpha gathered here, once) and the
+  // output slot of each target.
+  const bool last = d == pass->last_pass;
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int j = tid + r * kSortThreads;
+    if (j >= nvalid || outpos[r] == 0xffffffffu) continue;
+    const uint32_t out = outpos[r];
+    const uint32_t id = sid[j];
+    if (last) {
+      const bool src_pt = (int64_t)id < N;
+      b_out[out] = src_pt ? alpha[id] : T(0);
+      slot_out[out] = src_pt ? kNoSlot : (uint32_t)((int64_t)id - N);
+    } else {
+      iout[out] = id;
     }
   }
 }
@@ -300,8 +390,8 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(
 }  // namespace
 
 template <class T>
-hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, int64_t N,
-                       hipStream_t s, Timeline* tl) {
+hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, const T* alpha,
+                       int64_t N, double key_width, hipStream_t s, Timeline* tl) {
   constexpr int D = KeyOf<T>::kDigits;
   const int64_t P = M + N;
   tl->mark(s);
@@ -312,12 +402,14 @@ hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, in
   if (hb > kHistBlocks) hb = kHistBlocks;
   if (hb < 1) hb = 1;
   hipLaunchKernelGGL(k_histogram<T>, dim3((unsigned)hb), dim3(256), 0, s, x, y, N, P, w.hist,
-                     w.status);
-  hipLaunchKernelGGL(k_plan<T>, dim3(1), dim3(256), 0, s, w.hist, P, w.dig_off, w.pass);
+                     w.status, w.maxabs);
+  hipLaunchKernelGGL(k_plan<T>, dim3(1), dim3(256), 0, s, w.hist, P, w.maxabs, key_width, w.dig_off,
+                     w.pass);
   tl->mark(s);
   for (int d = 0; d < D; ++d) {
     hipLaunchKernelGGL(k_onesweep<T>, dim3((unsigned)w.sort_tiles), dim3(kSortThreads), 0, s, d, x,
-                       y, N, P, w.keys[0], w.keys[1], w.idx[0], w.idx[1], w.dig_off, w.pass,
+                       y, alpha, N, P, w.keys[0], w.keys[1], w.idx[0], w.idx[1], (T*)w.b, w.slot,
+                       w.dig_off, w.pass,
                        w.tile_ctr, w.lookback[d & 1], w.lookback[(d + 1) & 1], w.status);
     tl->mark(s);
   }
@@ -325,8 +417,8 @@ hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, in
 }
 
 template hipError_t sort_points<double>(const Workspace&, const double*, int64_t, const double*,
-                                        int64_t, hipStream_t, Timeline*);
+                                        const double*, int64_t, double, hipStream_t, Timeline*);
 template hipError_t sort_points<float>(const Workspace&, const float*, int64_t, const float*,
-                                       int64_t, hipStream_t, Timeline*);
+                                       const float*, int64_t, double, hipStream_t, Timeline*);
 
 }  // namespace fgt

@@ -97,6 +97,18 @@ def test_wide_spread_small_delta():
     full_check(x, y, a, 1e-6, 6, "spread")
 
 
+@pytest.mark.parametrize("delta", [1e-4, 1e-10])
+def test_near_duplicates_below_key_resolution(delta):
+    """Points a few ulps apart: the library may leave them unordered (its
+    key resolution); the result must stay within the stated bounds."""
+    g = np.random.default_rng(6)
+    base = g.random(300)
+    y = (base[g.integers(0, 300, 20000)] + g.integers(0, 64, 20000) * 2.0 ** -52)
+    x = (base[g.integers(0, 300, 15000)] + g.integers(0, 64, 15000) * 2.0 ** -52)
+    a = g.standard_normal(len(y))
+    full_check(x, y, a, delta, 6, "near-dup")
+
+
 def test_clustered_small():
     pr = W.clustered(log2n=15, log2m=13, delta=1e-5, digits=6, n_comp=16)
     full_check(pr.x, pr.y, pr.alpha, pr.delta, 6, "clustered-small")
