@@ -56,7 +56,8 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   w.lookback[1] = (uint64_t*)take(sizeof(uint64_t) * (size_t)w.sort_tiles * kRadix);
   w.dig_off = (uint32_t*)take(sizeof(uint32_t) * digits * kRadix);
   w.pass = (PassInfo*)take(sizeof(PassInfo));
-  w.agg = take((size_t)esz * 6 * (size_t)n_modes * (size_t)w.scan_tiles);
+  w.agg = take((size_t)esz * kAggStride * (size_t)n_modes * (size_t)w.scan_tiles);
+  w.tile_k = (int32_t*)take(sizeof(int32_t) * (size_t)w.scan_tiles);
   w.carry = take((size_t)esz * 4 * (size_t)n_modes * (size_t)w.scan_tiles);
   w.keys[0] = take((size_t)esz * (size_t)P);
   w.keys[1] = take((size_t)esz * (size_t)P);
@@ -167,6 +168,17 @@ int fgt_plan(double delta, int digits, int dtype, fgt_plan_t* out) {
       if (b <= target) lo = s; else hi = s;
     }
     p->modes.key_width = lo * sqrt(delta);
+  }
+  for (int k = 0; k < tab->n_modes; ++k) {
+    double cr = 1.0, ci = 0.0;
+    for (int m = 0; m <= fgt::kTaylorMax; ++m) {
+      p->modes.coef_re[k][m] = cr;
+      p->modes.coef_im[k][m] = ci;
+      const double nr = (-p->modes.tau_re[k] * cr + p->modes.tau_im[k] * ci) / (m + 1);
+      const double ni = (-p->modes.tau_re[k] * ci - p->modes.tau_im[k] * cr) / (m + 1);
+      cr = nr;
+      ci = ni;
+    }
   }
   // Taylor thresholds for the element type's unit roundoff.
   const double unit = dtype == FGT_F64 ? ldexp(1.0, -53) : ldexp(1.0, -24);

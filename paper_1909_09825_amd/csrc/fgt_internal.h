@@ -35,6 +35,9 @@ struct Modes {
   double tau_abs_max;
   double taylor_thr[kTaylorMax + 1];
   double key_width;   // sort resolution in coordinate units (see fgt_plan)
+  // Taylor coefficients of exp(-tau_k x) in x: (-tau_k)^m / m!.
+  double coef_re[FGT_MAX_MODES][kTaylorMax + 1];
+  double coef_im[FGT_MAX_MODES][kTaylorMax + 1];
 };
 
 // ---------------------------------------------------------------------------
@@ -56,6 +59,11 @@ constexpr int kScanWaves = kScanThreads / kWave;
 constexpr int kScanChunk = 8;
 constexpr int kScanTile = kScanThreads * kScanChunk;   // 2048 points per tile
 constexpr int kCarryThreads = 1024;
+// Per tile and mode the reduce kernel stores A, F, G and the two factors
+// exp(-tau hf), exp(-tau hg) that move the tile carries to its centre.
+constexpr int kAggStride = 10;
+// Tiles whose moment count is at most this take the fast final kernel.
+constexpr int kFastMoments = 12;
 
 
 template <class T> struct KeyOf;
@@ -115,7 +123,8 @@ struct Workspace {
   uint64_t* lookback[2]; // [sort_tiles][256]; [0] zeroed per call, each pass clears the other
   uint32_t* dig_off;     // [digits][256]
   PassInfo* pass;
-  void* agg;             // [scan_tiles][modes][6] scalars: A, F, G (complex)
+  void* agg;             // [scan_tiles][modes][kAggStride] scalars (complex A, F, G, eF, eG)
+  int32_t* tile_k;       // [scan_tiles] moments used for the tile, -1 if it is too wide
   void* carry;           // [scan_tiles][modes][4] scalars: CF, CB (complex)
   size_t zero_bytes;     // bytes from `status` that the first kernel clears
   int64_t sort_tiles, scan_tiles;

@@ -125,7 +125,8 @@ template <class T, int NM>
 __global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void* keys1,
                                                   const PassInfo* __restrict__ pass,
                                                   const T* __restrict__ bs, int64_t P, Modes md,
-                                                  T* __restrict__ agg) {
+                                                  T* __restrict__ agg,
+                                                  int32_t* __restrict__ tile_k) {
   const void* keys = pass->final_buf ? keys1 : keys0;
   const int lane = threadIdx.x;
   const int64_t tile = blockIdx.x;
@@ -152,6 +153,7 @@ __global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void*
     }
     if (t * er > T(Prec<T>::kUnit)) K = -1;   // too wide: use the recurrences
   }
+  if (lane == 0) tile_k[tile] = K;
 
   if (K >= 0) {
     T mu[kMomentMax + 1];
@@ -199,10 +201,12 @@ __global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void*
       const C<T> a = exp_neg_general<T>(tr, ti, span);
       const C<T> f = cmul(ef, fs);
       const C<T> g = cmul(eg, gs);
-      T* o = agg + ((size_t)tile * NM + k) * 6;
+      T* o = agg + ((size_t)tile * NM + k) * kAggStride;
       o[0] = a.re; o[1] = a.im;
       o[2] = f.re; o[3] = f.im;
       o[4] = g.re; o[5] = g.im;
+      o[6] = ef.re; o[7] = ef.im;
+      o[8] = eg.re; o[9] = eg.im;
     }
     return;
   }
@@ -250,7 +254,7 @@ __global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void*
         sb.a = cmul(sb.a, rr.a);
       }
     }
-    T* o = agg + ((size_t)tile * NM + k) * 6;
+    T* o = agg + ((size_t)tile * NM + k) * kAggStride;
     if (lane == kWave - 1) {
       o[0] = pf.a.re; o[1] = pf.a.im;
       o[2] = pf.f.re; o[3] = pf.f.im;
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(const T* __restrict__ a
   const int64_t a1 = a0 + per < tiles ? a0 + per : tiles;
 
   auto tile_seg = [&](int64_t t) {
-    const T* p = agg + ((size_t)t * NM + k) * 6;
+    const T* p = agg + ((size_t)t * NM + k) * kAggStride;
     Seg<T> s;
     s.a = {p[0], p[1]};
     s.f = {p[2], p[3]};
@@ -360,7 +364,12 @@ __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const
                                                         const uint32_t* __restrict__ slots,
                                                         int64_t M, int64_t P, Modes md,
                                                         const T* __restrict__ carry,
+                                                        const int32_t* __restrict__ tile_k,
                                                         T* __restrict__ u) {
+  {
+    const int K = tile_k[blockIdx.x];
+    if (K >= 0 && K <= kFastMoments) return;   // handled by k_final_fast
+  }
   const void* keys = pass->final_buf ? keys1 : keys0;
   __shared__ Staged<T> st;
   __shared__ Seg<T> wtot[NM][kScanWaves][2];   // per wave: [0] forward total, [1] backward total
@@ -370,19 +379,26 @@ __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const
   const int64_t tile = blockIdx.x;
   const int64_t t0 = tile * kScanTile;
 
-  for (int e = tid; e < kScanTile; e += kScanThreads) {
-    const int64_t p = t0 + e;
-    T z = T(0), b = T(0);
-    uint32_t slot = kNoSlot;
-    if (p < P) {
-      z = key_value<T>(keys, p);
-      b = bs[p];
-      slot = slots[p];
+  {
+    // All of this thread's loads are issued before any is used.
+    constexpr int R = kScanTile / kScanThreads;
+    T zr[R], br[R];
+    uint32_t sr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t p = t0 + tid + r * kScanThreads;
+      const bool in = p < P;
+      zr[r] = in ? key_value<T>(keys, p) : T(0);
+      br[r] = in ? bs[p] : T(0);
+      sr[r] = in ? slots[p] : kNoSlot;
     }
-    const int q = lds_pos(e);
-    st.z[q] = z;
-    st.b[q] = b;
-    st.slot[q] = slot;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = lds_pos(tid + r * kScanThreads);
+      st.z[q] = zr[r];
+      st.b[q] = br[r];
+      st.slot[q] = sr[r];
+    }
   }
   T zprev = T(0);
   if (tid == 0) zprev = t0 > 0 ? key_value<T>(keys, t0 - 1) : T(0);
@@ -436,27 +452,14 @@ __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const
     C<T> ex[kScanChunk];
 #pragma unroll
     for (int j = 0; j < kScanChunk; ++j) ex[j] = {T(0), T(0)};
-    {
-      double cr = 1.0, ci = 0.0;   // (-tau)^m / m!, m = 0..kTaylorMax
-      double coef_re[kTaylorMax + 1], coef_im[kTaylorMax + 1];
 #pragma unroll
-      for (int m = 0; m <= kTaylorMax; ++m) {
-        coef_re[m] = cr;
-        coef_im[m] = ci;
-        const double nr = (-md.tau_re[k] * cr + md.tau_im[k] * ci) / (m + 1);
-        const double ni = (-md.tau_re[k] * ci - md.tau_im[k] * cr) / (m + 1);
-        cr = nr;
-        ci = ni;
-      }
+    for (int m = kTaylorMax; m >= 0; --m) {
+      if (m <= D) {
+        const T c_re = T(md.coef_re[k][m]), c_im = T(md.coef_im[k][m]);
 #pragma unroll
-      for (int m = kTaylorMax; m >= 0; --m) {
-        if (m <= D) {
-          const T c_re = T(coef_re[m]), c_im = T(coef_im[m]);
-#pragma unroll
-          for (int j = 0; j < kScanChunk; ++j) {
-            ex[j].re = fma(ex[j].re, dz[j], c_re);
-            ex[j].im = fma(ex[j].im, dz[j], c_im);
-          }
+        for (int j = 0; j < kScanChunk; ++j) {
+          ex[j].re = fma(ex[j].re, dz[j], c_re);
+          ex[j].im = fma(ex[j].im, dz[j], c_im);
         }
       }
     }
@@ -537,6 +540,211 @@ __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const
   }
 }
 
+// ---------------------------------------------------------------------------
+// k_final_fast: tiles short on the decay scale (moment count K known from
+// k_reduce).  The carry into each thread's chunk comes from the other chunks'
+// power moments about the tile centre c:
+//   h+ before the chunk  = E_f (CF eG + sum_m tau^m P_m / m!),    E_f = exp(-tau (z_s - c)),
+//   h- at its last point = E_b (CB eF + sum_m (-tau)^m S_m / m!), E_b = exp(-tau (c - z_e)),
+// with P_m / S_m the moments of the tile's points before / after the chunk,
+// CF, CB the tile carries, eF = exp(-tau hf), eG = exp(-tau hg) (from k_reduce).
+// The moments are mode-independent, so only two short Taylor series and two
+// Horner sums per chunk and mode remain besides the sweeps.
+// ---------------------------------------------------------------------------
+template <class T>
+union FastLds {
+  Staged<T> st;
+  struct {
+    T pre[kFastMoments + 1][kScanThreads];   // moments of the tile's points before each chunk
+    T suf[kFastMoments + 1][kScanThreads];   // ... and after it
+  } mom;
+};
+
+template <class T, int NM>
+__global__ __launch_bounds__(kScanThreads) void k_final_fast(
+    const void* keys0, const void* keys1, const PassInfo* __restrict__ pass,
+    const T* __restrict__ bs, const uint32_t* __restrict__ slots, int64_t M, int64_t P, Modes md,
+    const T* __restrict__ agg, const T* __restrict__ carry, const int32_t* __restrict__ tile_k,
+    T* __restrict__ u) {
+  const int64_t tile = blockIdx.x;
+  const int K = tile_k[tile];
+  if (K < 0 || K > kFastMoments) return;
+  const void* keys = pass->final_buf ? keys1 : keys0;
+  __shared__ FastLds<T> lds;
+  __shared__ T mtot[kFastMoments + 1][kScanWaves];
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int64_t t0 = tile * kScanTile;
+  const int n = (int)((P - t0) < kScanTile ? (P - t0) : kScanTile);
+
+  {
+    // All of this thread's loads are issued before any is used.
+    constexpr int R = kScanTile / kScanThreads;
+    T zr[R], br[R];
+    uint32_t sr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t p = t0 + tid + r * kScanThreads;
+      const bool in = p < P;
+      zr[r] = in ? key_value<T>(keys, p) : T(0);
+      br[r] = in ? bs[p] : T(0);
+      sr[r] = in ? slots[p] : kNoSlot;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = lds_pos(tid + r * kScanThreads);
+      lds.st.z[q] = zr[r];
+      lds.st.b[q] = br[r];
+      lds.st.slot[q] = sr[r];
+    }
+  }
+  const T zfirst = key_value<T>(keys, t0);
+  const T zprev = t0 > 0 ? key_value<T>(keys, t0 - 1) : zfirst;
+  const T zlast = key_value<T>(keys, t0 + n - 1);
+  const T c = zprev + (zlast - zprev) * T(0.5);
+  __syncthreads();
+
+  // Chunk: gaps, strengths, offsets from the centre, slots, the point before
+  // it (zs) and its last point (ze).
+  const int e0 = tid * kScanChunk;
+  T dz[kScanChunk], bb[kScanChunk], sc[kScanChunk];
+  uint32_t myslot[kScanChunk];
+  T dzmax = T(0);
+  T zl = tid == 0 ? zprev : (e0 - 1 < n ? lds.st.z[lds_pos(e0 - 1)] : zlast);
+  const T zs = zl;
+#pragma unroll
+  for (int j = 0; j < kScanChunk; ++j) {
+    const int e = e0 + j;
+    const bool valid = e < n;
+    const T zj = lds.st.z[lds_pos(e)];
+    dz[j] = valid ? zj - zl : T(0);
+    bb[j] = lds.st.b[lds_pos(e)];
+    sc[j] = valid ? zj - c : T(0);
+    myslot[j] = lds.st.slot[lds_pos(e)];
+    zl = valid ? zj : zl;
+    dzmax = dz[j] > dzmax ? dz[j] : dzmax;
+  }
+  const T ze = zl;
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) {
+    const T other = shfl_xor(dzmax, o);
+    dzmax = other > dzmax ? other : dzmax;
+  }
+  __syncthreads();   // the staging area becomes the moment tables
+
+  // Chunk moments nu_m = sum_j b_j (z_j - c)^m, their in-wave inclusive sums
+  // (into pre) and the chunk's own values (into suf) for now.
+  {
+    T pw[kScanChunk];
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) pw[j] = bb[j];
+    for (int m = 0; m <= K; ++m) {
+      T nu = T(0);
+#pragma unroll
+      for (int j = 0; j < kScanChunk; ++j) {
+        nu += pw[j];
+        pw[j] *= sc[j];
+      }
+      T inc = nu;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const T v = shfl_up(inc, o);
+        if (lane >= o) inc += v;
+      }
+      if (lane == kWave - 1) mtot[m][wave] = inc;
+      lds.mom.pre[m][tid] = inc;
+      lds.mom.suf[m][tid] = nu;
+    }
+  }
+  __syncthreads();
+  for (int m = 0; m <= K; ++m) {
+    T off = T(0), tot = T(0);
+#pragma unroll
+    for (int w = 0; w < kScanWaves; ++w) {
+      const T v = mtot[m][w];
+      if (w < wave) off += v;
+      tot += v;
+    }
+    const T inc = lds.mom.pre[m][tid];
+    const T nu = lds.mom.suf[m][tid];
+    lds.mom.pre[m][tid] = off + (inc - nu);   // before the chunk
+    lds.mom.suf[m][tid] = (tot - off) - inc;  // after the chunk
+  }
+
+  T acc[kScanChunk];
+#pragma unroll
+  for (int j = 0; j < kScanChunk; ++j) acc[j] = T(0);
+  const T xf = zs - c;
+  const T xb = c - ze;
+
+#pragma unroll 1
+  for (int k = 0; k < NM; ++k) {
+    const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
+    const T om_re = T(md.om_re[k]), om_im = T(md.om_im[k]);
+
+    // Carries into the chunk.  exp(-tau xf), exp(-tau xb) with |tau x| <= r:
+    // degree K suffices; sum_m tau^m P_m / m! and sum_m (-tau)^m S_m / m! by Horner.
+    C<T> ef = {T(0), T(0)}, eb = {T(0), T(0)}, fs = {T(0), T(0)}, gs = {T(0), T(0)};
+    for (int m = K; m >= 0; --m) {
+      const T c_re = T(md.coef_re[k][m]), c_im = T(md.coef_im[k][m]);
+      ef.re = fma(ef.re, xf, c_re);
+      ef.im = fma(ef.im, xf, c_im);
+      eb.re = fma(eb.re, xb, c_re);
+      eb.im = fma(eb.im, xb, c_im);
+      const T f = T(kInvFact.v[m]);
+      fs = cfma(fs, C<T>{tr, ti}, C<T>{lds.mom.pre[m][tid] * f, T(0)});
+      gs = cfma(gs, C<T>{-tr, -ti}, C<T>{lds.mom.suf[m][tid] * f, T(0)});
+    }
+    const T* ag = agg + ((size_t)tile * NM + k) * kAggStride;
+    const T* cr = carry + ((size_t)tile * NM + k) * 4;
+    const C<T> tf = cfma(C<T>{cr[0], cr[1]}, C<T>{ag[8], ag[9]}, fs);   // CF eG + fs
+    const C<T> tb = cfma(C<T>{cr[2], cr[3]}, C<T>{ag[6], ag[7]}, gs);   // CB eF + gs
+
+    // Mode exponentials of the chunk's gaps.
+    const double rr = md.tau_abs[k] * (double)dzmax;
+    int D = kTaylorMax;
+#pragma unroll
+    for (int d = kTaylorMax; d >= 1; --d)
+      if (rr <= md.taylor_thr[d]) D = d;
+    const T dz_lim = T(md.taylor_thr[kTaylorMax] / md.tau_abs[k]);
+    C<T> ex[kScanChunk];
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) ex[j] = {T(0), T(0)};
+#pragma unroll
+    for (int m = kTaylorMax; m >= 0; --m) {
+      if (m <= D) {
+        const T c_re = T(md.coef_re[k][m]), c_im = T(md.coef_im[k][m]);
+#pragma unroll
+        for (int j = 0; j < kScanChunk; ++j) {
+          ex[j].re = fma(ex[j].re, dz[j], c_re);
+          ex[j].im = fma(ex[j].im, dz[j], c_im);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j)
+      if (dz[j] > dz_lim) ex[j] = exp_neg_general<T>(tr, ti, dz[j]);
+
+    C<T> h = cmul(ef, tf);
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) {
+      h = cfma(ex[j], h, C<T>{bb[j], T(0)});
+      acc[j] = fma(om_re, h.re, fma(-om_im, h.im, acc[j]));
+    }
+    C<T> g = cmul(eb, tb);
+#pragma unroll
+    for (int j = kScanChunk - 1; j >= 0; --j) {
+      acc[j] = fma(om_re, g.re, fma(-om_im, g.im, acc[j]));
+      g = cmul(ex[j], cadd(g, C<T>{bb[j], T(0)}));
+    }
+  }
+
+#pragma unroll
+  for (int j = 0; j < kScanChunk; ++j)
+    if ((int64_t)myslot[j] < M) u[myslot[j]] = acc[j];
+}
+
 template <class T>
 __global__ void k_fill_zero(T* __restrict__ u, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -550,13 +758,16 @@ hipError_t scan_nm(const Workspace& w, const Modes& md, int64_t M, int64_t N, T*
   const int64_t P = M + N;
   const dim3 grid((unsigned)w.scan_tiles);
   hipLaunchKernelGGL((k_reduce<T, NM>), grid, dim3(kWave), 0, s, w.keys[0], w.keys[1], w.pass,
-                     (const T*)w.b, P, md, (T*)w.agg);
+                     (const T*)w.b, P, md, (T*)w.agg, w.tile_k);
   tl->mark(s);
   hipLaunchKernelGGL((k_carry<T, NM>), dim3(NM), dim3(kCarryThreads), 0, s, (const T*)w.agg,
                      w.scan_tiles, (T*)w.carry);
   tl->mark(s);
+  hipLaunchKernelGGL((k_final_fast<T, NM>), grid, dim3(kScanThreads), 0, s, w.keys[0], w.keys[1],
+                     w.pass, (const T*)w.b, w.slot, M, P, md, (const T*)w.agg, (const T*)w.carry,
+                     w.tile_k, u);
   hipLaunchKernelGGL((k_final<T, NM>), grid, dim3(kScanThreads), 0, s, w.keys[0], w.keys[1], w.pass,
-                     (const T*)w.b, w.slot, M, P, md, (const T*)w.carry, u);
+                     (const T*)w.b, w.slot, M, P, md, (const T*)w.carry, w.tile_k, u);
   tl->mark(s);
   return hipGetLastError();
 }

@@ -63,20 +63,31 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
   bool bad = false;
   T zmax = T(0);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += stride) {
-    const T z = load_point(x, y, N, p);
-    bad |= !isfinite(z);
-    zmax = fabs(z) > zmax ? fabs(z) : zmax;
-    const K k = to_key(z);
+  constexpr int kBatch = 8;   // loads issued together before they are used
+  for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p0 < P; p0 += stride * kBatch) {
+    T zb[kBatch];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const uint32_t dig = (uint32_t)(k >> (8 * d)) & 0xffu;
-      if (cnt[d] != 0u && dig != cur[d]) {
-        atomicAdd(&h[d * kRadix + cur[d]], cnt[d]);
-        cnt[d] = 0u;
+    for (int i = 0; i < kBatch; ++i) {
+      const int64_t p = p0 + i * stride;
+      zb[i] = p < P ? load_point(x, y, N, p) : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      if (p0 + i * stride >= P) break;
+      const T z = zb[i];
+      bad |= !isfinite(z);
+      zmax = fabs(z) > zmax ? fabs(z) : zmax;
+      const K k = to_key(z);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const uint32_t dig = (uint32_t)(k >> (8 * d)) & 0xffu;
+        if (cnt[d] != 0u && dig != cur[d]) {
+          atomicAdd(&h[d * kRadix + cur[d]], cnt[d]);
+          cnt[d] = 0u;
+        }
+        cur[d] = dig;
+        ++cnt[d];
       }
-      cur[d] = dig;
-      ++cnt[d];
     }
   }
 #pragma unroll
@@ -182,6 +193,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   __shared__ uint32_t tstart[kRadix];             // tile-local exclusive digit starts
   __shared__ uint64_t gbase[kRadix];              // global output position of each digit's run
   __shared__ uint32_t wsum[kRadix / kWave];
+  __shared__ uint32_t thist[kRadix];               // tile digit histogram
   __shared__ K stage[kSortTile];                  // keys, then (reused) payloads, in digit order
   __shared__ int s_tile;
 
@@ -197,6 +209,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   }
   if (tid == 0) s_tile = (int)atomicAdd(&tile_ctr[d], 1u);
   for (int i = tid; i < kSortWaves * kRadix; i += kSortThreads) (&wcnt[0][0])[i] = 0u;
+  if (tid < kRadix) thist[tid] = 0u;
   __syncthreads();
   const int tile = s_tile;
   const bool digit_thread = tid < kRadix;   // threads 0..255 own one digit value each
@@ -232,6 +245,19 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     }
   }
 
+  // Tile histogram first, so the tile's counts are published before the
+  // (longer) stable ranking and successors waiting on them move on sooner.
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i)
+    if (base + i * kWave + lane < P) atomicAdd(&thist[(uint32_t)(key[i] >> shift) & 0xffu], 1u);
+  __syncthreads();
+  uint32_t tcount = 0u;
+  if (digit_thread) {
+    tcount = thist[tid];
+    __hip_atomic_store(&lb_cur[(size_t)tile * kRadix + tid], kFlagAgg | (uint64_t)tcount,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+
   // Stable ranking inside the wave, items in order (i, lane): lanes with the
   // same digit are found with 8 ballots; the lowest lane of each group
   // advances the wave's running count.
@@ -256,22 +282,6 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     __builtin_amdgcn_wave_barrier();
     rank[i] = before + below;
   }
-  __syncthreads();
-
-  // Tile histogram, wave offsets, publish the tile's aggregate.
-  uint32_t tcount = 0u;
-  if (digit_thread) {
-    uint32_t run_sum = 0u;
-#pragma unroll
-    for (int w = 0; w < kSortWaves; ++w) {
-      const uint32_t c = wcnt[w][tid];
-      wcnt[w][tid] = run_sum;
-      run_sum += c;
-    }
-    tcount = run_sum;
-    __hip_atomic_store(&lb_cur[(size_t)tile * kRadix + tid], kFlagAgg | (uint64_t)tcount,
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
 
   // Exclusive scan of the tile histogram over digits (thread tid owns digit tid).
   {
@@ -287,22 +297,60 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
       uint32_t before = 0u;
       for (int w = 0; w < wave; ++w) before += wsum[w];
       tstart[tid] = before + incl - tcount;
+      // running per-wave counts -> exclusive wave offsets
+      uint32_t run_sum = 0u;
+#pragma unroll
+      for (int w = 0; w < kSortWaves; ++w) {
+        const uint32_t c = wcnt[w][tid];
+        wcnt[w][tid] = run_sum;
+        run_sum += c;
+      }
     }
   }
 
-  // Decoupled look-back over earlier tiles for this digit, kLookWindow
-  // predecessors per round so their load latencies overlap.
+  // Decoupled look-back over earlier tiles for this digit.  The first round
+  // of loads is issued before the tile is sorted in LDS, so its latency is
+  // covered by that work.
+  uint64_t v0[kLookWindow];
+  const int jtop = tile - 1;
+  if (digit_thread) {
+#pragma unroll
+    for (int q = 0; q < kLookWindow; ++q)
+      v0[q] = (jtop - q >= 0) ? __hip_atomic_load(&lb_cur[(size_t)(jtop - q) * kRadix + tid],
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                              : kFlagPrefix;
+  }
+  __syncthreads();
+
+  // Sort the tile by digit in LDS (keys first, then payloads through the same
+  // buffer) and write each digit's run to its global position.
+  const int64_t tile_begin = (int64_t)tile * kSortTile;
+  const int nvalid = (int)((P - tile_begin) < kSortTile ? (P - tile_begin) : kSortTile);
+  uint32_t pos[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const uint32_t dig = (uint32_t)(key[i] >> shift) & 0xffu;
+    pos[i] = tstart[dig] + wcnt[wave][dig] + rank[i];
+    if (base + i * kWave + lane < P && pos[i] < (uint32_t)kSortTile) stage[pos[i]] = key[i];
+  }
+
   if (digit_thread) {
     uint64_t excl = 0ull;
     uint32_t spins = 0u;
-    int j = tile - 1;
+    int j = jtop;
+    bool first = true;
     while (j >= 0) {
       uint64_t v[kLookWindow];
 #pragma unroll
-      for (int q = 0; q < kLookWindow; ++q)
-        v[q] = (j - q >= 0) ? __hip_atomic_load(&lb_cur[(size_t)(j - q) * kRadix + tid],
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                            : kFlagPrefix;
+      for (int q = 0; q < kLookWindow; ++q) {
+        if (first)
+          v[q] = v0[q];
+        else
+          v[q] = (j - q >= 0) ? __hip_atomic_load(&lb_cur[(size_t)(j - q) * kRadix + tid],
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                              : kFlagPrefix;
+      }
+      first = false;
       int used = 0;
       bool done = false;
 #pragma unroll
@@ -329,19 +377,6 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     __hip_atomic_store(&lb_cur[(size_t)tile * kRadix + tid], kFlagPrefix | (excl + tcount),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     gbase[tid] = (uint64_t)dig_off[d * kRadix + tid] + excl;
-  }
-  __syncthreads();
-
-  // Sort the tile by digit in LDS (keys first, then payloads through the same
-  // buffer) and write each digit's run to its global position.
-  const int64_t tile_begin = (int64_t)tile * kSortTile;
-  const int nvalid = (int)((P - tile_begin) < kSortTile ? (P - tile_begin) : kSortTile);
-  uint32_t pos[kSortItems];
-#pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    const uint32_t dig = (uint32_t)(key[i] >> shift) & 0xffu;
-    pos[i] = tstart[dig] + wcnt[wave][dig] + rank[i];
-    if (base + i * kWave + lane < P && pos[i] < (uint32_t)kSortTile) stage[pos[i]] = key[i];
   }
   __syncthreads();
   // Each thread visits the same positions j in both write loops; the output
