@@ -16,7 +16,6 @@ the CPU oracle's SOE recurrence timed on a bounded sample of the same inputs.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -47,16 +46,9 @@ def parse():
     return ap.parse_args()
 
 
-def source_hash(paths):
-    h = hashlib.sha256()
-    for p in paths:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def traffic_for(kernel: str):
     """HBM bytes per launch from committed counter runs, if the kernel source is unchanged."""
+    from paper_1909_09825_amd.profiling import source_hash
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f).get(kernel)
@@ -64,7 +56,7 @@ def traffic_for(kernel: str):
         return None
     if not rec or rec.get("source_sha") != source_hash(rec["sources"]):
         return None
-    return rec["bytes_per_launch"]
+    return int(rec["bytes_per_launch"])
 
 
 def cpu_baseline(x, y, a, delta, digits, n_modes, k):
@@ -143,25 +135,36 @@ def main():
     n_modes = p.n_modes
     per_step = {k: v / calls for k, v in phases.items()}
     radix = {k: v for k, v in per_step.items() if k.startswith("radix")}
+    # Passes whose digit is constant or below the key resolution return at once;
+    # only the data-moving launches count as launches of the sort kernel.
+    longest = max(radix.values()) if radix else 0.0
+    moving = [k for k, v in radix.items() if v > 0.05 * longest]
+    n_run = len(moving)
     groups = {
-        "k_onesweep": sum(radix.values()),
-        "k_tiles_final": per_step.get("tiles_final", 0.0),
-        "k_tiles_reduce": per_step.get("tiles_reduce", 0.0),
+        "k_onesweep": sum(radix[k] for k in moving),
+        "k_final": per_step.get("tiles_final", 0.0),
+        "k_reduce": per_step.get("tiles_reduce", 0.0),
         "setup": per_step.get("setup", 0.0),
         "k_carry": per_step.get("carry", 0.0),
     }
     dominant = max(groups, key=groups.get)
-    # Algorithmic bytes per launch.
-    n_passes = len(radix)
-    sort_bytes_first = P * (esz + esz + 4)          # read coordinate, write key + index
-    sort_bytes_rest = P * 2 * (esz + 4)             # read and write key + index
-    scan_read = P * (esz + 4) + N * esz             # keys + index, gathered alpha
+    # Algorithmic bytes per launch.  First pass: read the coordinate, write key
+    # and index; middle passes: read and write key and index; last pass: read
+    # key and index, gather alpha for the sources, write key, strength, slot.
+    first = P * (esz + esz + 4)
+    middle = P * 2 * (esz + 4)
+    last = P * (esz + 4) + N * esz + P * (2 * esz + 4)
+    if n_run <= 1:
+        sort_bytes = P * esz + N * esz + P * (2 * esz + 4)
+    else:
+        sort_bytes = (first + (n_run - 2) * middle + last) / n_run
+    scan_read = P * (2 * esz)                        # keys and strengths
     alg = {
-        "k_onesweep": (sort_bytes_first + (n_passes - 1) * sort_bytes_rest) / max(n_passes, 1),
-        "k_tiles_final": scan_read + M * esz,        # + u scattered
-        "k_tiles_reduce": scan_read,
+        "k_onesweep": sort_bytes,
+        "k_final": scan_read + P * 4 + M * esz,      # + slots, + u scattered
+        "k_reduce": scan_read,
     }
-    launches = {"k_onesweep": n_passes, "k_tiles_final": 1, "k_tiles_reduce": 1}
+    launches = {"k_onesweep": max(n_run, 1), "k_final": 1, "k_reduce": 1}
 
     def roof(kernel):
         ms_launch = groups[kernel] / launches[kernel]
@@ -172,7 +175,7 @@ def main():
     gbs, ms_launch = roof(dom)
     traffic = traffic_for(dom)
     kernels = {}
-    for k in ("k_onesweep", "k_tiles_reduce", "k_tiles_final"):
+    for k in ("k_onesweep", "k_reduce", "k_final"):
         g, ms = roof(k)
         kernels[k] = {"ms_per_launch": round(ms, 5), "launches_per_step": launches[k],
                       "alg_bytes_per_launch": int(alg[k]), "GBps": round(g, 1),
@@ -200,6 +203,7 @@ def main():
         },
         "roofline": {
             "kernel": dom,
+            "ms_per_launch": round(ms_launch, 5),
             "bound": "hbm",
             "achieved": round(gbs, 1),
             "peak": HBM_PEAK_GBS,

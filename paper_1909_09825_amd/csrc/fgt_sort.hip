@@ -308,18 +308,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     }
   }
 
-  // Decoupled look-back over earlier tiles for this digit.  The first round
-  // of loads is issued before the tile is sorted in LDS, so its latency is
-  // covered by that work.
-  uint64_t v0[kLookWindow];
   const int jtop = tile - 1;
-  if (digit_thread) {
-#pragma unroll
-    for (int q = 0; q < kLookWindow; ++q)
-      v0[q] = (jtop - q >= 0) ? __hip_atomic_load(&lb_cur[(size_t)(jtop - q) * kRadix + tid],
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                              : kFlagPrefix;
-  }
   __syncthreads();
 
   // Sort the tile by digit in LDS (keys first, then payloads through the same
@@ -334,30 +323,33 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     if (base + i * kWave + lane < P && pos[i] < (uint32_t)kSortTile) stage[pos[i]] = key[i];
   }
 
+  // Decoupled look-back over earlier tiles for this digit (after the LDS sort,
+  // which gives predecessors time to publish).
   if (digit_thread) {
+    // Consume predecessors nearest first: aggregates are added, a prefix ends
+    // the walk.  A predecessor that has not published yet is polled alone,
+    // with back-off, so waiting costs one uncached word per poll.
     uint64_t excl = 0ull;
     uint32_t spins = 0u;
     int j = jtop;
-    bool first = true;
-    while (j >= 0) {
+    bool done = j < 0;
+    while (!done) {
       uint64_t v[kLookWindow];
 #pragma unroll
       for (int q = 0; q < kLookWindow; ++q) {
-        if (first)
-          v[q] = v0[q];
-        else
           v[q] = (j - q >= 0) ? __hip_atomic_load(&lb_cur[(size_t)(j - q) * kRadix + tid],
                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                               : kFlagPrefix;
       }
-      first = false;
       int used = 0;
-      bool done = false;
+      bool stalled = false;
 #pragma unroll
       for (int q = 0; q < kLookWindow; ++q) {
-        if (!done && used == q) {
+        if (!done && !stalled) {
           const uint64_t f = v[q] & ~kValueMask;
-          if (f != 0ull) {
+          if (f == 0ull) {
+            stalled = true;
+          } else {
             excl += v[q] & kValueMask;
             ++used;
             done = f == kFlagPrefix;
@@ -365,13 +357,25 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
         }
       }
       j -= used;
-      if (done) break;
-      if (used == 0) {
-        if (++spins > kSpinLimit) {
+      if (done || j < 0) break;
+      if (stalled) {
+        uint32_t backoff = 1u;
+        uint64_t w;
+        while (true) {
+          w = __hip_atomic_load(&lb_cur[(size_t)j * kRadix + tid], __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+          if ((w & ~kValueMask) != 0ull) break;
+          if (++spins > kSpinLimit) break;
+          for (uint32_t b = 0; b < backoff; ++b) __builtin_amdgcn_s_sleep(2);
+          if (backoff < 16u) backoff <<= 1;
+        }
+        if (spins > kSpinLimit) {
           atomicOr(status, kStatusInternal);
           break;
         }
-        __builtin_amdgcn_s_sleep(1);
+        excl += w & kValueMask;
+        --j;
+        done = (w & ~kValueMask) == kFlagPrefix;
       }
     }
     __hip_atomic_store(&lb_cur[(size_t)tile * kRadix + tid], kFlagPrefix | (excl + tcount),
