@@ -21,7 +21,9 @@ Construction (the paper's Sections 2.2, 2.4 and 3.4):
   kernels take the real part of the mode sum (Section 1, after (1.3)).
 * Measure E_m on the grid of (3.1) (delta = 1, x = 0 and 1e5 log-spaced
   points on [1e-5, 1e2]) and on a denser check grid; the shipped bound is
-  the larger of the two.  E'_m, the derivative error, is measured the same way.
+  the larger of the two plus a relative margin of 1e-3 (the sup between grid
+  points is slightly larger than any grid maximum).  E'_m, the derivative
+  error, is measured the same way, with a margin of 1e-2.
 
 Run from the repository root:  python -m paper_1909_09825_amd.soe.gen_tables
 """
@@ -137,8 +139,8 @@ def build_tables():
             "n_modes": m,
             "tau0_re": tau0.real.tolist(), "tau0_im": tau0.imag.tolist(),
             "omega_re": omega.real.tolist(), "omega_im": omega.imag.tolist(),
-            "err_grid": e1, "err_bound": max(e1, e2),
-            "deriv_err_bound": max(ep1, ep2),
+            "err_grid": e1, "err_bound": max(e1, e2) * (1.0 + 1e-3),
+            "deriv_err_bound": max(ep1, ep2) * (1.0 + 1e-2),
             "sum_abs_omega": float(np.sum(np.abs(omega))),
         })
     return tables

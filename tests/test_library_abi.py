@@ -1,0 +1,115 @@
+"""The C ABI on the CPU: the library loads, exports every function the header
+declares, and its host-side paths (plans, tables, validation) behave as
+documented.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1909_09825_amd as fgt
+from paper_1909_09825_amd import _lib
+from oracle import soe_table
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fgt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fgt_\w+)\s*\(", text)))
+
+
+def test_header_symbols_are_exported():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 12
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_plan_selects_smallest_table():
+    expect = {3: 2, 6: 4, 9: 6, 11: 7}
+    for d, m in expect.items():
+        p = fgt.plan(1e-4, d)
+        assert p.n_modes == m
+        assert p.err_bound <= 10.0 ** (-d)
+
+
+def test_plan_scales_nodes_by_sqrt_delta():
+    a = fgt.plan(1.0, 6)
+    b = fgt.plan(1e-4, 6)
+    np.testing.assert_allclose(b.tau, a.tau / 1e-2, rtol=1e-15)
+    np.testing.assert_array_equal(a.omega, b.omega)
+    assert a.err_bound == b.err_bound
+
+
+@pytest.mark.parametrize("delta,digits,dtype,exc", [
+    (0.0, 6, "f64", ValueError), (-1.0, 6, "f64", ValueError), (float("nan"), 6, "f64", ValueError),
+    (float("inf"), 6, "f64", ValueError), (1e-3, 0, "f64", ValueError), (1e-3, 99, "f64", ValueError),
+    (1e-3, 9, "f32", fgt.FGTError),
+])
+def test_plan_rejects_bad_arguments(delta, digits, dtype, exc):
+    import torch
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    with pytest.raises(exc):
+        fgt.plan(delta, digits, dt)
+
+
+def test_plan_codes_through_the_c_abi():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.fgt_plan(1e-3, 6, 0, None) == fgt.FGT_EINVAL
+    assert lib.fgt_plan(1e-3, 6, 7, ctypes.byref(h)) == fgt.FGT_EINVAL
+    assert lib.fgt_plan(1e-3, 7, fgt.FGT_F32, ctypes.byref(h)) == fgt.FGT_EUNSUPPORTED
+    assert lib.fgt_plan(1e-3, 6, fgt.FGT_F64, ctypes.byref(h)) == fgt.FGT_OK
+    assert lib.fgt_plan_info(None, None, None, None, None, None, None) == fgt.FGT_EINVAL
+    assert lib.fgt_workspace_size(None, 10, 10) == 0
+    assert lib.fgt_workspace_size(h, -1, 10) == 0
+    assert lib.fgt_workspace_size(h, 10, 10) > 0
+    assert lib.fgt_max_digits(fgt.FGT_F32) == 6 and lib.fgt_max_digits(5) == 0
+    assert lib.fgt_strerror(fgt.FGT_ENONFINITE).decode() == "non-finite coordinate"
+    lib.fgt_plan_destroy(h)
+    lib.fgt_plan_destroy(None)
+
+
+def test_eval_validation_happens_before_any_launch():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.fgt_plan(1e-3, 6, fgt.FGT_F64, ctypes.byref(h)) == fgt.FGT_OK
+    dummy = ctypes.c_void_p(256)
+    ok_ws = lib.fgt_workspace_size(h, 4, 4)
+    # bad plan, negative sizes, too many points, null pointers, small or misaligned workspace
+    assert lib.fgt_eval(None, dummy, 4, dummy, dummy, 4, dummy, dummy, ok_ws, None) == fgt.FGT_EINVAL
+    assert lib.fgt_eval(h, dummy, -1, dummy, dummy, 4, dummy, dummy, ok_ws, None) == fgt.FGT_EINVAL
+    assert lib.fgt_eval(h, dummy, 1 << 31, dummy, dummy, 1 << 31, dummy, dummy, ok_ws, None) == fgt.FGT_EINVAL
+    assert lib.fgt_eval(h, None, 4, dummy, dummy, 4, dummy, dummy, ok_ws, None) == fgt.FGT_EINVAL
+    assert lib.fgt_eval(h, dummy, 4, None, dummy, 4, dummy, dummy, ok_ws, None) == fgt.FGT_EINVAL
+    assert lib.fgt_eval(h, dummy, 4, dummy, dummy, 4, dummy, None, ok_ws, None) == fgt.FGT_EINVAL
+    assert lib.fgt_eval(h, dummy, 4, dummy, dummy, 4, dummy, dummy, ok_ws - 1, None) == fgt.FGT_EINVAL
+    assert lib.fgt_eval(h, dummy, 4, dummy, dummy, 4, dummy, ctypes.c_void_p(257), ok_ws, None) == fgt.FGT_EINVAL
+    assert lib.fgt_eval(h, dummy, 0, dummy, dummy, 4, dummy, dummy, ok_ws, None) == fgt.FGT_OK   # M = 0: nothing
+    lib.fgt_plan_destroy(h)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6, 7])
+def test_shipped_tables_equal_the_oracles(otables, m):
+    """The library's generator and the oracle's build the same tables independently."""
+    digits = {1: 1, 2: 3, 3: 5, 4: 6, 5: 8, 6: 10, 7: 11}[m]
+    p = fgt.plan(1.0, digits)
+    assert p.n_modes == m
+    np.testing.assert_array_equal(p.tau, otables[m]["tau0"])
+    np.testing.assert_array_equal(p.omega, otables[m]["omega"])
+
+
+@pytest.mark.parametrize("digits", [1, 3, 5, 6, 8, 10, 11])
+def test_stated_bound_is_honest(digits):
+    """The oracle re-measures the shipped table on the (3.1) grid and a finer one."""
+    p = fgt.plan(1.0, digits)
+    e, ep, _ = soe_table.table_errors(p.tau, p.omega)
+    fine = np.concatenate([[0.0], np.logspace(-8.0, 2.0, 400001)])
+    e2, ep2, _ = soe_table.table_errors(p.tau, p.omega, fine)
+    assert max(e, e2) <= p.err_bound * (1 + 1e-12)
+    assert max(ep, ep2) <= p.deriv_err_bound * 1.01
