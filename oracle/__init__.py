@@ -7,6 +7,8 @@ library (``paper_1909_09825_amd``) and the GPU library never imports it.
 * :func:`direct`          -- O1, the definition (1.1)-(1.2), Neumaier-summed.
 * :func:`soe_recurrence`  -- O2, the SOE sweeps of Section 4 ((4.1)-(4.6)).
 * :func:`soe_brute`       -- O3, the SOE transform summed pair by pair.
+* :func:`direct_gradients` -- gradients of L = sum_i g_i u_i from the definition.
+* :func:`soe_deriv_brute` -- the SOE transform's derivative field, pair by pair.
 * :mod:`oracle.soe_table` -- the SOE tables built from Sections 2-3 and the
   E_n measurement (3.1).
 
@@ -58,6 +60,12 @@ def _load():
         lib.oracle_soe_brute.argtypes = [dp, i64, dp, dp, i64, ctypes.c_double, ctypes.c_int,
                                          dp, dp, dp, dp, dp, ctypes.c_int]
         lib.oracle_soe_brute.restype = ctypes.c_int
+        lib.oracle_direct_field.argtypes = [dp, i64, dp, dp, i64, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_int, dp, ctypes.c_int, ctypes.c_int]
+        lib.oracle_direct_field.restype = ctypes.c_int
+        lib.oracle_soe_deriv_brute.argtypes = [dp, i64, dp, dp, i64, ctypes.c_double, ctypes.c_int,
+                                               dp, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int]
+        lib.oracle_soe_deriv_brute.restype = ctypes.c_int
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -118,3 +126,51 @@ def soe_brute(x, y, alpha, delta: float, tau0, omega, threads: int = 0) -> np.nd
     if rc:
         raise ValueError(f"oracle_soe_brute failed ({rc})")
     return u
+
+
+def _field(x, y, w, delta, which, cutoff=DEFAULT_CUTOFF, threads=0, plant=0):
+    x, y, w = _f64(x), _f64(y), _f64(w)
+    out = np.zeros(x.shape[0], np.float64)
+    rc = _load().oracle_direct_field(_ptr(x), x.shape[0], _ptr(y), _ptr(w), y.shape[0], float(delta),
+                                     float(cutoff), int(which), _ptr(out), int(threads), int(plant))
+    if rc:
+        raise ValueError(f"oracle_direct_field failed ({rc})")
+    return out
+
+
+def direct_gradients(x, y, alpha, g, delta: float, targets=None, sources=None, threads: int = 0,
+                     plant: int = 0):
+    """Gradients of L = sum_i g_i u_i, u from (1.1)-(1.2), by direct summation.
+
+    Returns (dalpha, dx, dy, ddelta):
+      dalpha_j = sum_i g_i G(x_i - y_j)            (the transform with roles swapped),
+      dx_i     = g_i sum_j alpha_j G'(x_i - y_j),
+      dy_j     = alpha_j sum_i g_i G'(y_j - x_i),
+      ddelta   = sum_ij g_i alpha_j (x_i - y_j)^2 / (4 delta^2) G(x_i - y_j).
+    `targets` / `sources` restrict dx / (dalpha, dy) to index subsets (ddelta is
+    then None).  `plant` is passed to the field evaluation (tests only).
+    """
+    x, y, alpha, g = _f64(x), _f64(y), _f64(alpha), _f64(g)
+    ti = np.arange(x.shape[0]) if targets is None else np.asarray(targets)
+    sj = np.arange(y.shape[0]) if sources is None else np.asarray(sources)
+    dalpha = direct(y[sj], x, g, delta, threads=threads)
+    dx = g[ti] * _field(x[ti], y, alpha, delta, 1, threads=threads, plant=plant)
+    dy = alpha[sj] * _field(y[sj], x, g, delta, 1, threads=threads, plant=plant)
+    ddelta = None
+    if targets is None and sources is None:
+        ddelta = float(np.dot(g, _field(x, y, alpha, delta, 2, threads=threads, plant=plant)))
+    return dalpha, dx, dy, ddelta
+
+
+def soe_deriv_brute(x, y, w, delta: float, tau0, omega, threads: int = 0,
+                    plant: int = 0) -> np.ndarray:
+    """sum_j w_j S'(x_i - y_j) with S' of the SOE (sign(0) = 0)."""
+    x, y, w = _f64(x), _f64(y), _f64(w)
+    tr, ti, wr, wi = _table_arrays(tau0, omega)
+    out = np.zeros(x.shape[0], np.float64)
+    rc = _load().oracle_soe_deriv_brute(_ptr(x), x.shape[0], _ptr(y), _ptr(w), y.shape[0],
+                                        float(delta), tr.shape[0], _ptr(tr), _ptr(ti), _ptr(wr),
+                                        _ptr(wi), _ptr(out), int(threads), int(plant))
+    if rc:
+        raise ValueError(f"oracle_soe_deriv_brute failed ({rc})")
+    return out

@@ -5,7 +5,7 @@
  * the benchmark's CPU-baseline leg may load it.  It shares no code, header,
  * table or helper with the GPU library, and the GPU library never calls it.
  *
- * Three computations, all in IEEE double precision (no fast-math):
+ * Five computations, all in IEEE double precision (no fast-math):
  *
  *   O1  oracle_direct         the definition (1.1)-(1.2):
  *                             u_i = sum_j alpha_j exp(-(x_i - y_j)^2 / (4 delta)),
@@ -19,6 +19,9 @@
  *                             u_i = sum_k Re(omega_k (h+_{k,i} + h-_{k,i})), (4.1).
  *   O3  oracle_soe_brute      the SOE sum written out, (1.3) inserted in (1.1):
  *                             u_i = sum_j alpha_j Re sum_k omega_k exp(-tau_k |x_i-y_j| / sqrt(delta)).
+ *   O4  oracle_direct_field   the Gaussian's x- and delta-derivatives summed
+ *                             directly (gradients of L = sum_i g_i u_i).
+ *   O5  oracle_soe_deriv_brute the SOE's x-derivative summed pair by pair.
  *
  * The SOE table is an input: tau0_k (nodes at delta = 1) and omega_k, one
  * representative per conjugate pair with its weight already doubled
@@ -288,6 +291,117 @@ int oracle_soe_brute(const double* x, int64_t M, const double* y, const double* 
       nsum_add(&acc, alpha[j] * s);
     }
     u[i] = acc.s + acc.c;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Gradient oracle, direct definition.  With L = sum_i g_i u_i and u of (1.1):
+ *   dL/dx_i = g_i sum_j alpha_j G'(x_i - y_j),  G'(r) = -(r / (2 delta)) G(r),
+ *   dL/dy_j = alpha_j sum_i g_i G'(y_j - x_i),
+ *   dL/dalpha_j = sum_i g_i G(x_i - y_j)          (oracle_direct with roles swapped),
+ *   dL/ddelta = sum_i g_i sum_j alpha_j (r^2 / (4 delta^2)) G(r).
+ * oracle_direct_field evaluates, at each entry of x,
+ *   which = 1:  sum_j w_j G'(x - y_j),
+ *   which = 2:  sum_j w_j (r^2 / (4 delta^2)) G(r),   r = x - y_j,
+ * windowed like oracle_direct.
+ * plant 1: G'(r) with the sign flipped.
+ * plant 2: G'(r) = -(r / delta) G(r) (the 2 dropped).
+ * plant 3: the delta-derivative factor r^2 / (4 delta) (one 1/delta dropped).
+ * ---------------------------------------------------------------------- */
+int oracle_direct_field(const double* x, int64_t K, const double* y, const double* w, int64_t N,
+                        double delta, double cutoff, int which, double* out, int nthreads,
+                        int plant) {
+  if (K < 0 || N < 0 || !(delta > 0) || (which != 1 && which != 2)) return 1;
+  if (K == 0) return 0;
+  if (N == 0) {
+    for (int64_t i = 0; i < K; ++i) out[i] = 0.0;
+    return 0;
+  }
+  vi_t* ys = sorted_copy(y, N);
+  double* ws = (double*)malloc(sizeof(double) * (size_t)N);
+  if (!ys || !ws) {
+    free(ys);
+    free(ws);
+    return 2;
+  }
+  for (int64_t j = 0; j < N; ++j) ws[j] = w[ys[j].i];
+  const double denom = 4.0 * delta;
+  const double half_width = cutoff > 0 ? sqrt(denom * cutoff) : INFINITY;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < K; ++i) {
+    const double xi = x[i];
+    int64_t lo = 0, hi = N;
+    if (isfinite(half_width)) {
+      int64_t a = 0, b = N;
+      while (a < b) {
+        int64_t m = a + (b - a) / 2;
+        if (ys[m].v < xi - half_width) a = m + 1; else b = m;
+      }
+      lo = a;
+      a = lo;
+      b = N;
+      while (a < b) {
+        int64_t m = a + (b - a) / 2;
+        if (ys[m].v <= xi + half_width) a = m + 1; else b = m;
+      }
+      hi = a;
+    }
+    nsum_t acc = {0.0, 0.0};
+    for (int64_t j = lo; j < hi; ++j) {
+      const double r = xi - ys[j].v;
+      const double gk = exp(-(r * r) / denom);
+      double f;
+      if (which == 1) {
+        f = -(r / (2.0 * delta)) * gk;
+        if (plant == 1) f = -f;
+        if (plant == 2) f = -(r / delta) * gk;
+      } else {
+        f = (r * r) / (denom * delta) * gk;
+        if (plant == 3) f = (r * r) / denom * gk;
+      }
+      nsum_add(&acc, ws[j] * f);
+    }
+    out[i] = acc.s + acc.c;
+  }
+  free(ys);
+  free(ws);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Derivative of the SOE transform, pair by pair:
+ *   out_i = sum_j w_j S'(x_i - y_j),
+ *   S'(r) = Re sum_k omega_k (-tau_k) sign(r) exp(-tau_k |r|),  tau_k = tau0_k / sqrt(delta),
+ * with sign(0) = 0 (the Gaussian's derivative vanishes at 0).
+ * plant 1: sign(0) = +1 (a coincident source counted as one to the left).
+ * plant 2: the sign factor dropped (derivative of exp(-tau r) without |r|).
+ * ---------------------------------------------------------------------- */
+int oracle_soe_deriv_brute(const double* x, int64_t M, const double* y, const double* w, int64_t N,
+                           double delta, int n_modes, const double* tau_re, const double* tau_im,
+                           const double* om_re, const double* om_im, double* out, int nthreads,
+                           int plant) {
+  if (M < 0 || N < 0 || n_modes < 0 || !(delta > 0)) return 1;
+  const double sd = sqrt(delta);
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < M; ++i) {
+    nsum_t acc = {0.0, 0.0};
+    for (int64_t j = 0; j < N; ++j) {
+      const double r = x[i] - y[j];
+      if (r == 0.0 && plant != 1) continue;
+      double sg = r >= 0 ? 1.0 : -1.0;
+      if (plant == 2) sg = 1.0;
+      double s = 0.0;
+      for (int k = 0; k < n_modes; ++k) {
+        const double complex tau = (tau_re[k] + I * tau_im[k]) / sd;
+        const double complex om = om_re[k] + I * om_im[k];
+        s += creal(-om * tau * cexp(-tau * fabs(r)));
+      }
+      nsum_add(&acc, w[j] * sg * s);
+    }
+    out[i] = acc.s + acc.c;
   }
   return 0;
 }
