@@ -7,6 +7,7 @@ library (``paper_1909_09825_amd``) and the GPU library never imports it.
 * :func:`direct`          -- O1, the definition (1.1)-(1.2), Neumaier-summed.
 * :func:`soe_recurrence`  -- O2, the SOE sweeps of Section 4 ((4.1)-(4.6)).
 * :func:`soe_brute`       -- O3, the SOE transform summed pair by pair.
+* :func:`soe_recurrence_deriv` -- O2's sweeps giving the SOE transform's x-derivative.
 * :func:`direct_gradients` -- gradients of L = sum_i g_i u_i from the definition.
 * :func:`soe_deriv_brute` -- the SOE transform's derivative field, pair by pair.
 * :mod:`oracle.soe_table` -- the SOE tables built from Sections 2-3 and the
@@ -57,6 +58,10 @@ def _load():
         lib.oracle_soe_recurrence.argtypes = [dp, i64, dp, dp, i64, ctypes.c_double, ctypes.c_int,
                                               dp, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int]
         lib.oracle_soe_recurrence.restype = ctypes.c_int
+        lib.oracle_soe_recurrence_field.argtypes = [dp, i64, dp, dp, i64, ctypes.c_double,
+                                                    ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, dp,
+                                                    ctypes.c_int, ctypes.c_int]
+        lib.oracle_soe_recurrence_field.restype = ctypes.c_int
         lib.oracle_soe_brute.argtypes = [dp, i64, dp, dp, i64, ctypes.c_double, ctypes.c_int,
                                          dp, dp, dp, dp, dp, ctypes.c_int]
         lib.oracle_soe_brute.restype = ctypes.c_int
@@ -112,6 +117,21 @@ def soe_recurrence(x, y, alpha, delta: float, tau0, omega, threads: int = 0,
                                        _ptr(wi), _ptr(u), int(threads), int(plant))
     if rc:
         raise ValueError(f"oracle_soe_recurrence failed ({rc})")
+    return u
+
+
+def soe_recurrence_deriv(x, y, alpha, delta: float, tau0, omega, threads: int = 0,
+                         plant: int = 0) -> np.ndarray:
+    """O2 with derivative weights: sum_j alpha_j S'(x_i - y_j), a source at x_i counted left."""
+    x, y, alpha = _f64(x), _f64(y), _f64(alpha)
+    tr, ti, wr, wi = _table_arrays(tau0, omega)
+    u = np.zeros(x.shape[0], np.float64)
+    rc = _load().oracle_soe_recurrence_field(_ptr(x), x.shape[0], _ptr(y), _ptr(alpha), y.shape[0],
+                                             float(delta), tr.shape[0], _ptr(tr), _ptr(ti),
+                                             _ptr(wr), _ptr(wi), 1, _ptr(u), int(threads),
+                                             int(plant))
+    if rc:
+        raise ValueError(f"oracle_soe_recurrence_field failed ({rc})")
     return u
 
 

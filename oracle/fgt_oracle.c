@@ -187,11 +187,18 @@ int oracle_direct(const double* x, int64_t K, const double* y, const double* alp
  * plant 5: forward sweep stops when the sources run out (the loop guard of
  *          the printed fragment taken literally).
  * plant 6: backward source term uses exp(-tau (xs_i - y_j)) (sign flipped).
+ *
+ * With deriv = 1 the same sweeps give the x-derivative of the SOE transform,
+ * u'_i = sum_j alpha_j S'(x_i - y_j): a source left of x_i (h+) contributes
+ * d/dx exp(-tau (x - y)) = -tau exp(...), one to the right (h-) +tau exp(...),
+ * so the rows hold Re(-tau omega h+) and Re(+tau omega h-).  A source at x_i
+ * itself counts with h+ (sign +1), as the sweeps order it.
+ * plant 7 (deriv only): the h- rows keep the sign of the h+ rows.
  * ---------------------------------------------------------------------- */
-int oracle_soe_recurrence(const double* x, int64_t M, const double* y, const double* alpha,
-                          int64_t N, double delta, int n_modes, const double* tau_re,
-                          const double* tau_im, const double* om_re, const double* om_im,
-                          double* u, int nthreads, int plant) {
+int oracle_soe_recurrence_field(const double* x, int64_t M, const double* y, const double* alpha,
+                                int64_t N, double delta, int n_modes, const double* tau_re,
+                                const double* tau_im, const double* om_re, const double* om_im,
+                                int deriv, double* u, int nthreads, int plant) {
   if (M < 0 || N < 0 || n_modes < 0 || !(delta > 0)) return 1;
   if (M == 0) return 0;
   vi_t* xs = sorted_copy(x, M);
@@ -217,6 +224,7 @@ int oracle_soe_recurrence(const double* x, int64_t M, const double* y, const dou
     const double complex tau = (tau_re[k] + I * tau_im[k]) / sd;
     double complex om = om_re[k] + I * om_im[k];
     if (plant == 2) om *= 0.5;
+    if (deriv) om = (backward && plant != 7) ? tau * om : -tau * om;
     double* out = part + r * M;
     double complex h = 0.0;
     if (!backward) {
@@ -266,6 +274,14 @@ int oracle_soe_recurrence(const double* x, int64_t M, const double* y, const dou
   free(beta);
   free(part);
   return 0;
+}
+
+int oracle_soe_recurrence(const double* x, int64_t M, const double* y, const double* alpha,
+                          int64_t N, double delta, int n_modes, const double* tau_re,
+                          const double* tau_im, const double* om_re, const double* om_im,
+                          double* u, int nthreads, int plant) {
+  return oracle_soe_recurrence_field(x, M, y, alpha, N, delta, n_modes, tau_re, tau_im, om_re,
+                                     om_im, 0, u, nthreads, plant);
 }
 
 /* ------------------------------------------------------------------------

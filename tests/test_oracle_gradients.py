@@ -183,3 +183,30 @@ def test_soe_field_pin(otables, name):
 def test_planted_soe_field_mistake_is_caught(otables, plant):
     failed = [n for n, f in SOE_PINS.items() if not f(otables, plant)[0]]
     assert failed, f"plant {plant} passed every SOE field pin"
+
+
+# ---------------------------------------------------------------------------
+# O2 with derivative weights, pinned to O5 (itself pinned above)
+# ---------------------------------------------------------------------------
+
+def pin_recurrence_deriv(otables, plant=0):
+    worst = 0.0
+    for seed, (M, N, delta, m) in enumerate([(40, 50, 2e-3, 4), (33, 17, 1e-4, 6), (25, 60, 1.0, 2)]):
+        x, y, a, _, _ = problem(20 + seed, M=M, N=N, delta=delta)
+        t = otables[m]
+        d = oracle.soe_recurrence_deriv(x, y, a, delta, t["tau0"], t["omega"], plant=plant)
+        ref = oracle.soe_deriv_brute(x, y, a, delta, t["tau0"], t["omega"])
+        scale = np.abs(a).sum() * np.sum(np.abs(t["tau0"] * t["omega"])) / np.sqrt(delta)
+        worst = max(worst, float(np.max(np.abs(d - ref))) / scale)
+    return worst < 1e-13, f"O2' vs O5: {worst:.2e}"
+
+
+def test_recurrence_deriv_pin(otables):
+    ok, detail = pin_recurrence_deriv(otables)
+    assert ok, detail
+
+
+@pytest.mark.parametrize("plant", [2, 3, 4, 5, 6, 7])
+def test_planted_recurrence_deriv_mistake_is_caught(otables, plant):
+    ok, detail = pin_recurrence_deriv(otables, plant)
+    assert not ok, f"plant {plant} passed: {detail}"
