@@ -6,7 +6,10 @@ tile-scan reduce, carries, fused forward/backward sweeps, mode reduction and
 scatter) for M = N = 2^24 points uniform on [0,1), alpha ~ N(0,1),
 delta = 1e-4, 6 digits (4 modes), FP64, with inputs resident in HBM.
 
-Prints ONE JSON line.  `value` is (M+N) * modes / s.  `roofline` describes
+Prints ONE JSON line.  `value` is (M+N) * modes / s.  `fwd_bwd` times, on the
+same inputs, the forward followed by the adjoint (fgt_backward on the sorted
+workspace: dL/dalpha, dL/dx, dL/dy and dL/ddelta for L = g . u, g ~ N(0,1)).
+`roofline` describes
 the kernel with the largest share of the step, timed with HIP events recorded
 by the library on its own stream during the timed steps; `cpu_baseline` is
 the CPU oracle's SOE recurrence timed on a bounded sample of the same inputs.
@@ -41,6 +44,7 @@ def parse():
     ap.add_argument("--cpu-sample-log2n", type=int, default=22,
                     help="CPU oracle timed on the first 2^k targets and sources")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-grad", action="store_true", help="skip the fwd+bwd timing")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one plain device copy of this many bytes (counter calibration)")
     return ap.parse_args()
@@ -212,6 +216,25 @@ def main():
             "traffic": traffic,
         },
     }
+    if not args.no_grad:
+        G = torch.from_numpy(np.random.default_rng(5).standard_normal(M)).to(dev, dtype)
+        for _ in range(args.warmup):
+            fgt.eval(X, Y, A, p, out=u, ws=ws)
+            fgt.backward(X, Y, A, G, p, ws=ws, sorted=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fgt.eval(X, Y, A, p, out=u, ws=ws)
+            fgt.backward(X, Y, A, G, p, ws=ws, sorted=True)
+        torch.cuda.synchronize()
+        ms_fb = (time.perf_counter() - t0) * 1e3 / args.steps
+        out["fwd_bwd"] = {
+            "ms_per_step": round(ms_fb, 5),
+            "value": P * n_modes / (ms_fb * 1e-3),
+            "unit": "point-modes/s",
+            "ratio_to_fwd": round(ms_fb / ms_step, 4),
+            "step": "fgt_eval + fgt_backward(FGT_SORTED) giving dL/dalpha, dL/dx, dL/dy, dL/ddelta",
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr.x, pr.y, pr.alpha, args.delta, args.digits, n_modes,
                                            min(args.cpu_sample_log2n, args.log2n))

@@ -114,6 +114,47 @@ size_t fgt_workspace_size(fgt_plan_t plan, int64_t M, int64_t N);
 int fgt_eval(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha,
              int64_t N, void* u, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Flag for fgt_backward: the workspace already holds the sort of (x, y). */
+#define FGT_SORTED 1
+
+/*
+ * fgt_eval_sorted -- fgt_eval for new strengths alpha[N] on points already
+ * sorted: `ws` must hold the sorted state that the last fgt_eval (or
+ * fgt_backward without FGT_SORTED) wrote for the same plan, M, N and point
+ * coordinates.  Only the strengths are gathered again, so repeated transforms
+ * with fixed points skip the radix sort (the sort of Section 4 depends on the
+ * coordinates alone).  A workspace that does not hold such a state gives
+ * unspecified values but no access outside u, alpha and ws.
+ * Errors: as fgt_eval.
+ */
+int fgt_eval_sorted(fgt_plan_t plan, int64_t M, int64_t N, const void* alpha, void* u, void* ws,
+                    size_t ws_bytes, hipStream_t stream);
+
+/*
+ * fgt_backward -- gradients of L = sum_i g_i u_i, u the transform of fgt_eval.
+ * With S the plan's SOE kernel and S' its x-derivative
+ * (S'(r) = Re sum_k (-tau_k omega_k) sign(r) exp(-tau_k |r|), sign(0) taken as the
+ * side the sort puts the pair on):
+ *   dalpha[j] = sum_i g_i S(y_j - x_i)                  transposed transform (sources
+ *                                                       and targets swapped),
+ *   dx[i]     = g_i sum_j alpha_j S'(x_i - y_j),
+ *   dy[j]     = alpha_j sum_i g_i S'(y_j - x_i),
+ *   ddelta[0] = -(sum_i x_i dx[i] + sum_j y_j dy[j]) / (2 delta)
+ * (the last from u(c x, c y; c^2 delta) = u(x, y; delta), which S obeys exactly
+ * because its nodes scale as 1/sqrt(delta)).  All are device arrays of the plan's
+ * type: g[M], dalpha[N], dx[M], dy[N], ddelta a single element.  Any output may
+ * be null to skip it, except that ddelta needs dx (if M > 0) and dy (if N > 0).
+ *   flags  0 or FGT_SORTED.  With FGT_SORTED the sort held in `ws` (see
+ *          fgt_eval_sorted) is reused and x, y are read only for ddelta;
+ *          otherwise the points are sorted first.
+ *   ws     as for fgt_eval; the call leaves the sorted state in it.
+ * M == 0 or N == 0 writes zeros to every requested output.
+ * Errors: as fgt_eval, plus FGT_EINVAL for unknown flags or ddelta without dx, dy.
+ */
+int fgt_backward(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha,
+                 int64_t N, const void* g, void* dalpha, void* dx, void* dy, void* ddelta,
+                 int flags, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /*
  * fgt_last_device_status -- synchronise `stream`, then read and clear the
  * status word that the last fgt_eval on workspace `ws` left there.

@@ -7,10 +7,11 @@ per mode as parallel scans, all in hand-written HIP kernels behind the C ABI
 of include/fgt.h.
 """
 from ._lib import (FGT_EDEVICE, FGT_EINVAL, FGT_ENONFINITE, FGT_EUNSUPPORTED, FGT_F32, FGT_F64,
-                   FGT_OK, FGTError, LIB_PATH)
-from .api import (Plan, eval, last_device_status, max_digits, plan, profile_begin, profile_end,
-                  workspace)
+                   FGT_OK, FGT_SORTED, FGTError, LIB_PATH)
+from .api import (GaussTransform, Plan, backward, eval, eval_sorted, gauss_transform,
+                  last_device_status, max_digits, plan, profile_begin, profile_end, workspace)
 
-__all__ = ["Plan", "plan", "eval", "workspace", "last_device_status", "max_digits", "FGTError",
+__all__ = ["Plan", "plan", "eval", "eval_sorted", "backward", "GaussTransform", "gauss_transform",
+           "workspace", "last_device_status", "max_digits", "FGTError",
            "FGT_OK", "FGT_EINVAL", "FGT_EUNSUPPORTED", "FGT_ENONFINITE", "FGT_EDEVICE",
-           "FGT_F64", "FGT_F32", "LIB_PATH", "profile_begin", "profile_end"]
+           "FGT_F64", "FGT_F32", "FGT_SORTED", "LIB_PATH", "profile_begin", "profile_end"]

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(PKG, "libfgt.so")
 FGT_OK, FGT_EINVAL, FGT_EUNSUPPORTED, FGT_ENONFINITE, FGT_EDEVICE = 0, 1, 2, 3, 4
 FGT_F64, FGT_F32 = 0, 1
 FGT_MAX_MODES = 8
+FGT_SORTED = 1
 
 _lib = None
 
@@ -45,6 +46,11 @@ def load() -> ctypes.CDLL:
     lib.fgt_workspace_size.restype = ctypes.c_size_t
     lib.fgt_eval.argtypes = [vp, vp, c_i64, vp, vp, c_i64, vp, vp, ctypes.c_size_t, vp]
     lib.fgt_eval.restype = c_int
+    lib.fgt_eval_sorted.argtypes = [vp, c_i64, c_i64, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.fgt_eval_sorted.restype = c_int
+    lib.fgt_backward.argtypes = [vp, vp, c_i64, vp, vp, c_i64, vp, vp, vp, vp, vp, c_int, vp,
+                                 ctypes.c_size_t, vp]
+    lib.fgt_backward.restype = c_int
     lib.fgt_last_device_status.argtypes = [vp, vp]
     lib.fgt_last_device_status.restype = c_int
     lib.fgt_strerror.argtypes = [c_int]

@@ -125,6 +125,118 @@ def eval(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor, p: Plan,
     return out
 
 
+def _check_ws(p: Plan, ws: torch.Tensor, M: int, N: int, dev) -> int:
+    need = p.workspace_size(M, N)
+    if (not isinstance(ws, torch.Tensor) or ws.numel() * ws.element_size() < need
+            or not ws.is_contiguous() or ws.device != dev):
+        raise ValueError(f"workspace must be a contiguous {dev} tensor of >= {need} bytes")
+    return need
+
+
+def eval_sorted(alpha: torch.Tensor, p: Plan, ws: torch.Tensor, M: int,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """u for new strengths on the points whose sort `ws` holds (from eval or backward).
+
+    The radix sort depends on the coordinates only, so a sequence of
+    transforms with fixed x, y and changing alpha pays for it once.
+    """
+    if not isinstance(alpha, torch.Tensor) or not alpha.is_cuda:
+        raise ValueError("alpha must be a CUDA (HIP) tensor")
+    dev = alpha.device
+    alpha = _vec(alpha, "alpha", p.dtype, dev)
+    N = alpha.shape[0]
+    if out is None:
+        out = torch.empty(int(M), dtype=p.dtype, device=dev)
+    else:
+        out = _vec(out, "out", p.dtype, dev)
+        if out.shape[0] != M:
+            raise ValueError("out must have length M")
+    need = _check_ws(p, ws, M, N, dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    check(p._lib.fgt_eval_sorted(p.handle, int(M), N, alpha.data_ptr(), out.data_ptr(),
+                                 ws.data_ptr(), need, stream), "fgt_eval_sorted")
+    return out
+
+
+def backward(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor, g: torch.Tensor, p: Plan,
+             ws: torch.Tensor | None = None, sorted: bool = False, dalpha: bool = True,
+             dx: bool = True, dy: bool = True, ddelta: bool = True):
+    """Gradients of L = sum_i g_i u_i: (dL/dalpha, dL/dx, dL/dy, dL/ddelta), None where not asked.
+
+    With sorted=True, `ws` must hold the sort of (x, y) left by eval/backward
+    with the same plan.  dL/ddelta is a 0-dim tensor; asking for it computes
+    dL/dx and dL/dy as well.
+    """
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise ValueError("x must be a CUDA (HIP) tensor")
+    dev = x.device
+    x = _vec(x, "x", p.dtype, dev)
+    y = _vec(y, "y", p.dtype, dev)
+    alpha = _vec(alpha, "alpha", p.dtype, dev)
+    g = _vec(g, "g", p.dtype, dev)
+    M, N = x.shape[0], y.shape[0]
+    if alpha.shape[0] != N or g.shape[0] != M:
+        raise ValueError("alpha must have length N and g length M")
+    if ws is None:
+        if sorted:
+            raise ValueError("sorted=True needs the workspace that holds the sort")
+        ws = workspace(p, M, N, dev)
+    need = _check_ws(p, ws, M, N, dev)
+    want_dx, want_dy = dx or ddelta, dy or ddelta
+    o_da = torch.empty(N, dtype=p.dtype, device=dev) if dalpha else None
+    o_dx = torch.empty(M, dtype=p.dtype, device=dev) if want_dx else None
+    o_dy = torch.empty(N, dtype=p.dtype, device=dev) if want_dy else None
+    o_dd = torch.empty((), dtype=p.dtype, device=dev) if ddelta else None
+    ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = p._lib.fgt_backward(p.handle, x.data_ptr(), M, y.data_ptr(), alpha.data_ptr(), N,
+                             g.data_ptr(), ptr(o_da), ptr(o_dx), ptr(o_dy), ptr(o_dd),
+                             _lib.FGT_SORTED if sorted else 0, ws.data_ptr(), need, stream)
+    check(rc, "fgt_backward")
+    return o_da, (o_dx if dx else None), (o_dy if dy else None), o_dd
+
+
+class GaussTransform(torch.autograd.Function):
+    """u = FGT(x, y, alpha; delta) with gradients in x, y, alpha and delta.
+
+    The forward keeps its workspace (the sort of the points) for the backward,
+    which runs the adjoint scans on the same sorted order.
+    """
+
+    @staticmethod
+    def forward(ctx, x, y, alpha, delta, digits):
+        d = float(delta.detach().item()) if isinstance(delta, torch.Tensor) else float(delta)
+        p = Plan(d, int(digits), x.dtype)
+        ws = workspace(p, x.shape[0], y.shape[0], x.device)
+        u = eval(x, y, alpha, p, ws=ws)
+        ctx.save_for_backward(x, y, alpha)
+        ctx.plan, ctx.ws = p, ws
+        ctx.delta_is_tensor = isinstance(delta, torch.Tensor)
+        ctx.delta_dtype = delta.dtype if ctx.delta_is_tensor else None
+        return u
+
+    @staticmethod
+    def backward(ctx, gu):
+        x, y, alpha = ctx.saved_tensors
+        nx, ny, na, nd = ctx.needs_input_grad[:4]
+        if not (nx or ny or na or nd):
+            return None, None, None, None, None
+        da, dx, dy, dd = backward(x, y, alpha, gu.to(x.dtype).contiguous(), ctx.plan, ctx.ws,
+                                  sorted=True, dalpha=na, dx=nx, dy=ny, ddelta=nd)
+        if dd is not None and ctx.delta_is_tensor:
+            dd = dd.to(ctx.delta_dtype)
+        return dx, dy, da, dd, None
+
+
+def gauss_transform(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor, delta,
+                    digits: int = 6) -> torch.Tensor:
+    """Differentiable u_i = sum_j exp(-(x_i - y_j)^2 / (4 delta)) alpha_j (SOE at `digits`).
+
+    delta may be a float or a 0-dim tensor (then dL/ddelta is returned too).
+    """
+    return GaussTransform.apply(x, y, alpha, delta, digits)
+
+
 def last_device_status(ws: torch.Tensor) -> int:
     """Synchronise the current stream; return and clear the device status of `ws` (0 = ok)."""
     stream = torch.cuda.current_stream(ws.device).cuda_stream

@@ -61,10 +61,14 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   w.carry = take((size_t)esz * 4 * (size_t)n_modes * (size_t)w.scan_tiles);
   w.keys[0] = take((size_t)esz * (size_t)P);
   w.keys[1] = take((size_t)esz * (size_t)P);
+  // The two permutation buffers are consecutive; after the sort they hold the
+  // transposed strengths (esz * P <= 2 * align_up(4 * P) bytes).
   w.idx[0] = (uint32_t*)take(sizeof(uint32_t) * (size_t)P);
   w.idx[1] = (uint32_t*)take(sizeof(uint32_t) * (size_t)P);
+  w.bt = (void*)w.idx[0];
   w.b = take((size_t)esz * (size_t)P);
-  w.slot = (uint32_t*)take(sizeof(uint32_t) * (size_t)P);
+  w.ids = (uint32_t*)take(sizeof(uint32_t) * (size_t)P);
+  w.red = (double*)take(sizeof(double) * kRedBlocks);
   w.total = off;
   return w;
 }
@@ -89,6 +93,70 @@ struct fgt_plan_s {
   const fgt::SoeTable* table;
   fgt::Modes modes;
 };
+
+namespace fgt {
+namespace {
+
+// Sort (when `sort` is set) and evaluate u at the targets.
+template <class T>
+hipError_t forward(const fgt_plan_s* plan, const Workspace& w, const void* x, int64_t M,
+                   const void* y, const void* alpha, int64_t N, void* u, bool sort,
+                   hipStream_t s, Timeline* tl) {
+  const int64_t P = M + N;
+  hipError_t e = hipSuccess;
+  if (sort) {
+    e = sort_points<T>(w, (const T*)x, M, (const T*)y, (const T*)alpha, N, plan->modes.key_width,
+                       s, tl);
+  } else {
+    e = gather_strengths<T>(w, P, 0u, (uint32_t)N, (const T*)alpha, (T*)w.b, s);
+  }
+  if (e != hipSuccess) return e;
+  const ScanOut<T> out{(T*)u, nullptr, nullptr, (uint32_t)N, (uint32_t)M};
+  return scan_points<T>(w, plan->modes, P, (const T*)w.b, out, s, tl);
+}
+
+// Gradients of L = sum_i g_i u_i (see fgt_backward).
+template <class T>
+hipError_t backward(const fgt_plan_s* plan, const Workspace& w, const void* x, int64_t M,
+                    const void* y, const void* alpha, int64_t N, const void* g, void* dalpha,
+                    void* dx, void* dy, void* ddelta, bool sort, hipStream_t s) {
+  const int64_t P = M + N;
+  Timeline none;
+  hipError_t e = hipSuccess;
+  if (sort) {
+    e = sort_points<T>(w, (const T*)x, M, (const T*)y, (const T*)alpha, N, plan->modes.key_width,
+                       s, &none);
+  } else if (dx) {
+    e = gather_strengths<T>(w, P, 0u, (uint32_t)N, (const T*)alpha, (T*)w.b, s);
+  }
+  if (e != hipSuccess) return e;
+  if (dx) {
+    // dL/dx_i = g_i sum_j alpha_j S'(x_i - y_j): sources alpha, outputs at the targets.
+    const ScanOut<T> out{nullptr, (T*)dx, (const T*)g, (uint32_t)N, (uint32_t)M};
+    e = scan_points<T>(w, plan->modes, P, (const T*)w.b, out, s, &none);
+    if (e != hipSuccess) return e;
+  }
+  if (dalpha || dy) {
+    // Transposed: strengths g at the targets, outputs at the sources.
+    //   dL/dalpha_j = sum_i g_i S(y_j - x_i),  dL/dy_j = alpha_j sum_i g_i S'(y_j - x_i).
+    e = gather_strengths<T>(w, P, (uint32_t)N, (uint32_t)M, (const T*)g, (T*)w.bt, s);
+    if (e != hipSuccess) return e;
+    const ScanOut<T> out{(T*)dalpha, (T*)dy, (const T*)alpha, 0u, (uint32_t)N};
+    e = scan_points<T>(w, plan->modes, P, (const T*)w.bt, out, s, &none);
+    if (e != hipSuccess) return e;
+  }
+  if (ddelta) {
+    // u(c x, c y; c^2 delta) = u(x, y; delta) gives
+    //   dL/ddelta = -(sum_i x_i dL/dx_i + sum_j y_j dL/dy_j) / (2 delta),
+    // and translation invariance lets the coordinates be taken about any centre.
+    e = delta_gradient<T>(w, P, (const T*)x, (const T*)dx, M, (const T*)y, (const T*)dy, N,
+                          plan->delta, (T*)ddelta, s);
+  }
+  return e;
+}
+
+}  // namespace
+}  // namespace fgt
 
 extern "C" {
 
@@ -141,6 +209,8 @@ int fgt_plan(double delta, int digits, int dtype, fgt_plan_t* out) {
     p->modes.om_re[k] = tab->om_re[k];
     p->modes.om_im[k] = tab->om_im[k];
     p->modes.tau_abs[k] = hypot(p->modes.tau_re[k], p->modes.tau_im[k]);
+    p->modes.dom_re[k] = -(p->modes.tau_re[k] * tab->om_re[k] - p->modes.tau_im[k] * tab->om_im[k]);
+    p->modes.dom_im[k] = -(p->modes.tau_re[k] * tab->om_im[k] + p->modes.tau_im[k] * tab->om_re[k]);
     if (p->modes.tau_abs[k] > p->modes.tau_abs_max) p->modes.tau_abs_max = p->modes.tau_abs[k];
   }
   // Sort resolution.  Two points closer than w = s_w sqrt(delta) may be left in
@@ -249,20 +319,69 @@ int fgt_eval(fgt_plan_t plan, const void* x, int64_t M, const void* y, const voi
     tl.ev = call.ev;
     tl.cap = fgt::kMaxPhases + 1;
   }
-  hipError_t e;
-  if (f64) {
-    e = fgt::sort_points<double>(w, (const double*)x, M, (const double*)y, (const double*)alpha, N,
-                                 plan->modes.key_width, stream, &tl);
-    if (e == hipSuccess) e = fgt::scan_points<double>(w, plan->modes, M, N, (double*)u, stream, &tl);
-  } else {
-    e = fgt::sort_points<float>(w, (const float*)x, M, (const float*)y, (const float*)alpha, N,
-                                plan->modes.key_width, stream, &tl);
-    if (e == hipSuccess) e = fgt::scan_points<float>(w, plan->modes, M, N, (float*)u, stream, &tl);
-  }
+  hipError_t e = f64 ? fgt::forward<double>(plan, w, x, M, y, alpha, N, u, true, stream, &tl)
+                     : fgt::forward<float>(plan, w, x, M, y, alpha, N, u, true, stream, &tl);
   if (fgt::g_prof.on) {
     call.n = tl.n;
     fgt::g_prof.calls.push_back(call);
   }
+  return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+}
+
+int fgt_eval_sorted(fgt_plan_t plan, int64_t M, int64_t N, const void* alpha, void* u, void* ws,
+                    size_t ws_bytes, hipStream_t stream) {
+  if (!plan || M < 0 || N < 0) return FGT_EINVAL;
+  if (M + N >= (int64_t(1) << 32)) return FGT_EINVAL;
+  if (M == 0) return FGT_OK;
+  if (!u) return FGT_EINVAL;
+  const bool f64 = plan->dtype == FGT_F64;
+  if (N == 0) {
+    hipError_t e = f64 ? fgt::fill_zero<double>((double*)u, M, stream)
+                       : fgt::fill_zero<float>((float*)u, M, stream);
+    return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+  }
+  if (!alpha || !ws) return FGT_EINVAL;
+  if (((uintptr_t)ws & 255u) != 0) return FGT_EINVAL;
+  const fgt::Workspace w = fgt::layout(ws, M + N, f64 ? 8 : 4, plan->modes.n);
+  if (ws_bytes < w.total) return FGT_EINVAL;
+  fgt::Timeline none;
+  hipError_t e = f64 ? fgt::forward<double>(plan, w, nullptr, M, nullptr, alpha, N, u, false, stream, &none)
+                     : fgt::forward<float>(plan, w, nullptr, M, nullptr, alpha, N, u, false, stream, &none);
+  return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+}
+
+int fgt_backward(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha,
+                 int64_t N, const void* g, void* dalpha, void* dx, void* dy, void* ddelta,
+                 int flags, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!plan || M < 0 || N < 0) return FGT_EINVAL;
+  if (M + N >= (int64_t(1) << 32)) return FGT_EINVAL;
+  if (flags & ~FGT_SORTED) return FGT_EINVAL;
+  if (ddelta && ((M > 0 && !dx) || (N > 0 && !dy))) return FGT_EINVAL;
+  const bool f64 = plan->dtype == FGT_F64;
+  auto zero = [&](void* p, int64_t n) -> hipError_t {
+    if (!p || n == 0) return hipSuccess;
+    return f64 ? fgt::fill_zero<double>((double*)p, n, stream)
+               : fgt::fill_zero<float>((float*)p, n, stream);
+  };
+  if (M == 0 || N == 0) {
+    // No pairs: every gradient is zero.
+    hipError_t e = zero(dalpha, N);
+    if (e == hipSuccess) e = zero(dy, N);
+    if (e == hipSuccess) e = zero(dx, M);
+    if (e == hipSuccess) e = zero(ddelta, 1);
+    return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+  }
+  if (!dalpha && !dx && !dy && !ddelta) return FGT_OK;
+  if (!g || !alpha || !ws) return FGT_EINVAL;
+  const bool sort = !(flags & FGT_SORTED);
+  if ((sort || ddelta) && (!x || !y)) return FGT_EINVAL;
+  if (((uintptr_t)ws & 255u) != 0) return FGT_EINVAL;
+  const fgt::Workspace w = fgt::layout(ws, M + N, f64 ? 8 : 4, plan->modes.n);
+  if (ws_bytes < w.total) return FGT_EINVAL;
+  hipError_t e = f64 ? fgt::backward<double>(plan, w, x, M, y, alpha, N, g, dalpha, dx, dy, ddelta,
+                                            sort, stream)
+                     : fgt::backward<float>(plan, w, x, M, y, alpha, N, g, dalpha, dx, dy, ddelta,
+                                           sort, stream);
   return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
 }
 

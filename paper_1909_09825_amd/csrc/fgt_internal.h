@@ -38,7 +38,25 @@ struct Modes {
   // Taylor coefficients of exp(-tau_k x) in x: (-tau_k)^m / m!.
   double coef_re[FGT_MAX_MODES][kTaylorMax + 1];
   double coef_im[FGT_MAX_MODES][kTaylorMax + 1];
+  // Weights of the derivative field: d/dx exp(-tau |x|) = -tau sign(x) exp(-tau |x|),
+  // so S'(x) = Re sum_k dom_k sign(x) exp(-tau_k |x|) with dom_k = -tau_k omega_k.
+  double dom_re[FGT_MAX_MODES], dom_im[FGT_MAX_MODES];
 };
+
+// What the final scan kernel writes.  Sorted point p carries its merged index
+// id_p; it is an output point when o = id_p - t_lo < t_n, and then
+//   val[o] = sum_k Re(omega_k (h+ + h-))                      (the transform, (4.1))
+//   der[o] = scale[o] * sum_k Re(dom_k (h+ - h-))             (its x-derivative)
+// (scale null: factor 1).  The unsigned compare keeps every write in bounds.
+template <class T>
+struct ScanOut {
+  T* val;
+  T* der;
+  const T* scale;
+  uint32_t t_lo, t_n;
+};
+constexpr int kOutVal = 1;
+constexpr int kOutDer = 2;
 
 // ---------------------------------------------------------------------------
 // Tunables.
@@ -64,6 +82,8 @@ constexpr int kCarryThreads = 1024;
 constexpr int kAggStride = 10;
 // Tiles whose moment count is at most this take the fast final kernel.
 constexpr int kFastMoments = 12;
+// Blocks of the delta-gradient reduction.
+constexpr int kRedBlocks = 512;
 
 
 template <class T> struct KeyOf;
@@ -92,7 +112,7 @@ __device__ __forceinline__ float from_key(uint32_t k) {
   return __uint_as_float(b);
 }
 
-// Slot value of a source in the sorted sequence.
+// Merged index given to padding past the last point (never an output).
 constexpr uint32_t kNoSlot = 0xffffffffu;
 
 // Bits of the device status word.
@@ -106,7 +126,7 @@ struct PassInfo {
   int32_t run[8];     // 1 if radix pass d moves data
   int32_t src[8];     // 0/1: key buffer it reads, 2: the raw coordinates
   int32_t final_buf;  // buffer that holds the sorted keys at the end
-  int32_t last_pass;  // the last pass that runs; it also writes strengths and slots
+  int32_t last_pass;  // the last pass that runs; it also writes strengths and the final ids
   int32_t skipped_low;  // low digits left unsorted (below the plan's key resolution)
   int32_t pad[5];
 };
@@ -115,7 +135,10 @@ struct Workspace {
   void* keys[2];
   uint32_t* idx[2];
   void* b;               // [P] strength of each sorted point (alpha_j for a source, 0 for a target)
-  uint32_t* slot;        // [P] output index of each sorted target, kNoSlot for a source
+  uint32_t* ids;         // [P] merged index of each sorted point: j < N source j, else target j - N
+  void* bt;              // [P] strengths of the transposed transform (g_i at targets, 0 at
+                         //     sources); shares the permutation buffers, which are dead after the sort
+  double* red;           // [kRedBlocks] partial sums of the delta-gradient reduction
   uint32_t* status;      // [1] at offset 0, zeroed per call
   unsigned long long* maxabs;  // [1] largest |coordinate| as ordered bits, zeroed per call
   uint32_t* hist;        // [digits][256], zeroed per call
@@ -151,9 +174,20 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes);
 template <class T>
 hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, const T* alpha,
                        int64_t N, double key_width, hipStream_t s, Timeline* tl);
+// Scan of strengths `b` ([P], sorted order) over the sorted keys; writes what
+// `out` asks for.
 template <class T>
-hipError_t scan_points(const Workspace& w, const Modes& m, int64_t M, int64_t N, T* u,
-                       hipStream_t s, Timeline* tl);
+hipError_t scan_points(const Workspace& w, const Modes& m, int64_t P, const T* b,
+                       const ScanOut<T>& out, hipStream_t s, Timeline* tl);
+// b[p] = wts[id_p - lo] if that index is below n, else 0.
+template <class T>
+hipError_t gather_strengths(const Workspace& w, int64_t P, uint32_t lo, uint32_t n, const T* wts,
+                            T* b, hipStream_t s);
+// *out = -(sum_i (x_i - c) dx_i + sum_j (y_j - c) dy_j) / (2 delta), c the midpoint of
+// the sorted coordinates.
+template <class T>
+hipError_t delta_gradient(const Workspace& w, int64_t P, const T* x, const T* dx, int64_t M,
+                          const T* y, const T* dy, int64_t N, double delta, T* out, hipStream_t s);
 template <class T>
 hipError_t fill_zero(T* u, int64_t n, hipStream_t s);
 

@@ -1,14 +1,20 @@
 // The SOE recurrences of Section 4 as parallel affine scans on gfx950.
 //
 // After the sort, point p of the merged sequence has coordinate z_p,
-// strength b_p (alpha_j for source j, 0 for a target) and, for a target, its
-// output slot.  For mode k (tau = tau0_k / sqrt(delta)) let
+// strength b_p (alpha_j for source j, 0 for a target) and its merged index,
+// which names the output it feeds.  For mode k (tau = tau0_k / sqrt(delta)) let
 //     e_p = exp(-tau (z_p - z_{p-1})),   |e_p| <= 1 since z is sorted.
 // The forward recurrence (4.5) over the merged sequence is
 //     h+_p = e_p h+_{p-1} + b_p          (inclusive: sources at z_p count, (4.4))
 // and the backward recurrence (4.6), exclusive of the point itself, is
 //     h-_{p-1} = e_p (h-_p + b_p).
 // One factor e_p serves both.  At a target u_p = sum_k Re(omega_k (h+_p + h-_p)), (4.1).
+// The same sweeps give the x-derivative of the transform: h+ holds the sources
+// to the left (sign +1), h- those to the right (sign -1), so
+//     u'_p = sum_k Re(-tau_k omega_k (h+_p - h-_p)).
+// The gradients of L = sum_i g_i u_i are such scans with the roles of sources
+// and targets kept (dL/dx) or swapped (dL/dalpha, dL/dy: strengths g at the
+// targets, outputs at the sources).
 //
 // A segment [s, e) of the sequence acts on the two recurrences as
 //     h+_{e-1} = A h+_{s-1} + F,          h-_{s-1} = A h-_{e-1} + G,
@@ -25,7 +31,7 @@
 //              otherwise from the recurrences themselves.
 //   k_carry    per mode: exclusive prefix of F and suffix of G over tiles.
 //   k_final    per tile: chunk -> wave -> tile scans of both recurrences with
-//              the carries, sweeps, mode reduction, scatter u[slot] = value.
+//              the carries, sweeps, mode reduction, scatter to the outputs.
 #include "fgt_internal.h"
 
 namespace fgt {
@@ -352,20 +358,34 @@ template <class T>
 struct Staged {
   T z[kScanTile + kScanTile / kScanChunk];
   T b[kScanTile + kScanTile / kScanChunk];
-  uint32_t slot[kScanTile + kScanTile / kScanChunk];
+  uint32_t id[kScanTile + kScanTile / kScanChunk];
 };
+
+// Scatter of one chunk's results (see ScanOut).
+template <class T, int OUT>
+__device__ __forceinline__ void scatter_chunk(const ScanOut<T>& out, const uint32_t* ids,
+                                              const T* acc, const T* dacc) {
+#pragma unroll
+  for (int j = 0; j < kScanChunk; ++j) {
+    const uint32_t o = ids[j] - out.t_lo;
+    if (o < out.t_n) {
+      if (OUT & kOutVal) out.val[o] = acc[j];
+      if (OUT & kOutDer) out.der[o] = out.scale ? dacc[j] * out.scale[o] : dacc[j];
+    }
+  }
+}
 
 __device__ __forceinline__ int lds_pos(int e) { return e + e / kScanChunk; }
 
-template <class T, int NM>
+template <class T, int NM, int OUT>
 __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const void* keys1,
                                                         const PassInfo* __restrict__ pass,
                                                         const T* __restrict__ bs,
-                                                        const uint32_t* __restrict__ slots,
-                                                        int64_t M, int64_t P, Modes md,
+                                                        const uint32_t* __restrict__ ids,
+                                                        int64_t P, Modes md,
                                                         const T* __restrict__ carry,
                                                         const int32_t* __restrict__ tile_k,
-                                                        T* __restrict__ u) {
+                                                        ScanOut<T> out) {
   {
     const int K = tile_k[blockIdx.x];
     if (K >= 0 && K <= kFastMoments) return;   // handled by k_final_fast
@@ -390,14 +410,14 @@ __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const
       const bool in = p < P;
       zr[r] = in ? key_value<T>(keys, p) : T(0);
       br[r] = in ? bs[p] : T(0);
-      sr[r] = in ? slots[p] : kNoSlot;
+      sr[r] = in ? ids[p] : kNoSlot;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int q = lds_pos(tid + r * kScanThreads);
       st.z[q] = zr[r];
       st.b[q] = br[r];
-      st.slot[q] = sr[r];
+      st.id[q] = sr[r];
     }
   }
   T zprev = T(0);
@@ -432,14 +452,18 @@ __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const
     dzmax = other > dzmax ? other : dzmax;
   }
 
-  T acc[kScanChunk];
+  T acc[kScanChunk], dacc[kScanChunk];
 #pragma unroll
-  for (int j = 0; j < kScanChunk; ++j) acc[j] = T(0);
+  for (int j = 0; j < kScanChunk; ++j) {
+    acc[j] = T(0);
+    dacc[j] = T(0);
+  }
 
 #pragma unroll 1
   for (int k = 0; k < NM; ++k) {
     const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
     const T om_re = T(md.om_re[k]), om_im = T(md.om_im[k]);
+    const T dm_re = T(md.dom_re[k]), dm_im = T(md.dom_im[k]);
     // Degree D: smallest with (|tau| dzmax)^{D+1}/(D+1)! below the unit roundoff.
     const double rr = md.tau_abs[k] * (double)dzmax;
     int D = kTaylorMax;
@@ -522,22 +546,23 @@ __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const
 #pragma unroll
     for (int j = 0; j < kScanChunk; ++j) {
       h = cfma(ex[j], h, C<T>{bb[j], T(0)});
-      acc[j] = fma(om_re, h.re, fma(-om_im, h.im, acc[j]));
+      if (OUT & kOutVal) acc[j] = fma(om_re, h.re, fma(-om_im, h.im, acc[j]));
+      if (OUT & kOutDer) dacc[j] = fma(dm_re, h.re, fma(-dm_im, h.im, dacc[j]));
     }
     // Backward sweep: h- (exclusive) at every point.
     C<T> g = cb;
 #pragma unroll
     for (int j = kScanChunk - 1; j >= 0; --j) {
-      acc[j] = fma(om_re, g.re, fma(-om_im, g.im, acc[j]));
+      if (OUT & kOutVal) acc[j] = fma(om_re, g.re, fma(-om_im, g.im, acc[j]));
+      if (OUT & kOutDer) dacc[j] = fma(-dm_re, g.re, fma(dm_im, g.im, dacc[j]));
       g = cmul(ex[j], cadd(g, C<T>{bb[j], T(0)}));
     }
   }
 
+  uint32_t myid[kScanChunk];
 #pragma unroll
-  for (int j = 0; j < kScanChunk; ++j) {
-    const uint32_t slot = st.slot[lds_pos(e0 + j)];
-    if ((int64_t)slot < M) u[slot] = acc[j];
-  }
+  for (int j = 0; j < kScanChunk; ++j) myid[j] = st.id[lds_pos(e0 + j)];
+  scatter_chunk<T, OUT>(out, myid, acc, dacc);
 }
 
 // ---------------------------------------------------------------------------
@@ -560,12 +585,12 @@ union FastLds {
   } mom;
 };
 
-template <class T, int NM>
+template <class T, int NM, int OUT>
 __global__ __launch_bounds__(kScanThreads) void k_final_fast(
     const void* keys0, const void* keys1, const PassInfo* __restrict__ pass,
-    const T* __restrict__ bs, const uint32_t* __restrict__ slots, int64_t M, int64_t P, Modes md,
+    const T* __restrict__ bs, const uint32_t* __restrict__ ids, int64_t P, Modes md,
     const T* __restrict__ agg, const T* __restrict__ carry, const int32_t* __restrict__ tile_k,
-    T* __restrict__ u) {
+    ScanOut<T> out) {
   const int64_t tile = blockIdx.x;
   const int K = tile_k[tile];
   if (K < 0 || K > kFastMoments) return;
@@ -589,14 +614,14 @@ __global__ __launch_bounds__(kScanThreads) void k_final_fast(
       const bool in = p < P;
       zr[r] = in ? key_value<T>(keys, p) : T(0);
       br[r] = in ? bs[p] : T(0);
-      sr[r] = in ? slots[p] : kNoSlot;
+      sr[r] = in ? ids[p] : kNoSlot;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int q = lds_pos(tid + r * kScanThreads);
       lds.st.z[q] = zr[r];
       lds.st.b[q] = br[r];
-      lds.st.slot[q] = sr[r];
+      lds.st.id[q] = sr[r];
     }
   }
   const T zfirst = key_value<T>(keys, t0);
@@ -605,11 +630,11 @@ __global__ __launch_bounds__(kScanThreads) void k_final_fast(
   const T c = zprev + (zlast - zprev) * T(0.5);
   __syncthreads();
 
-  // Chunk: gaps, strengths, offsets from the centre, slots, the point before
+  // Chunk: gaps, strengths, offsets from the centre, ids, the point before
   // it (zs) and its last point (ze).
   const int e0 = tid * kScanChunk;
   T dz[kScanChunk], bb[kScanChunk], sc[kScanChunk];
-  uint32_t myslot[kScanChunk];
+  uint32_t myid[kScanChunk];
   T dzmax = T(0);
   T zl = tid == 0 ? zprev : (e0 - 1 < n ? lds.st.z[lds_pos(e0 - 1)] : zlast);
   const T zs = zl;
@@ -621,7 +646,7 @@ __global__ __launch_bounds__(kScanThreads) void k_final_fast(
     dz[j] = valid ? zj - zl : T(0);
     bb[j] = lds.st.b[lds_pos(e)];
     sc[j] = valid ? zj - c : T(0);
-    myslot[j] = lds.st.slot[lds_pos(e)];
+    myid[j] = lds.st.id[lds_pos(e)];
     zl = valid ? zj : zl;
     dzmax = dz[j] > dzmax ? dz[j] : dzmax;
   }
@@ -672,9 +697,12 @@ __global__ __launch_bounds__(kScanThreads) void k_final_fast(
     lds.mom.suf[m][tid] = (tot - off) - inc;  // after the chunk
   }
 
-  T acc[kScanChunk];
+  T acc[kScanChunk], dacc[kScanChunk];
 #pragma unroll
-  for (int j = 0; j < kScanChunk; ++j) acc[j] = T(0);
+  for (int j = 0; j < kScanChunk; ++j) {
+    acc[j] = T(0);
+    dacc[j] = T(0);
+  }
   const T xf = zs - c;
   const T xb = c - ze;
 
@@ -682,6 +710,7 @@ __global__ __launch_bounds__(kScanThreads) void k_final_fast(
   for (int k = 0; k < NM; ++k) {
     const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
     const T om_re = T(md.om_re[k]), om_im = T(md.om_im[k]);
+    const T dm_re = T(md.dom_re[k]), dm_im = T(md.dom_im[k]);
 
     // Carries into the chunk.  exp(-tau xf), exp(-tau xb) with |tau x| <= r:
     // degree K suffices; sum_m tau^m P_m / m! and sum_m (-tau)^m S_m / m! by Horner.
@@ -730,19 +759,19 @@ __global__ __launch_bounds__(kScanThreads) void k_final_fast(
 #pragma unroll
     for (int j = 0; j < kScanChunk; ++j) {
       h = cfma(ex[j], h, C<T>{bb[j], T(0)});
-      acc[j] = fma(om_re, h.re, fma(-om_im, h.im, acc[j]));
+      if (OUT & kOutVal) acc[j] = fma(om_re, h.re, fma(-om_im, h.im, acc[j]));
+      if (OUT & kOutDer) dacc[j] = fma(dm_re, h.re, fma(-dm_im, h.im, dacc[j]));
     }
     C<T> g = cmul(eb, tb);
 #pragma unroll
     for (int j = kScanChunk - 1; j >= 0; --j) {
-      acc[j] = fma(om_re, g.re, fma(-om_im, g.im, acc[j]));
+      if (OUT & kOutVal) acc[j] = fma(om_re, g.re, fma(-om_im, g.im, acc[j]));
+      if (OUT & kOutDer) dacc[j] = fma(-dm_re, g.re, fma(dm_im, g.im, dacc[j]));
       g = cmul(ex[j], cadd(g, C<T>{bb[j], T(0)}));
     }
   }
 
-#pragma unroll
-  for (int j = 0; j < kScanChunk; ++j)
-    if ((int64_t)myslot[j] < M) u[myslot[j]] = acc[j];
+  scatter_chunk<T, OUT>(out, myid, acc, dacc);
 }
 
 template <class T>
@@ -752,42 +781,121 @@ __global__ void k_fill_zero(T* __restrict__ u, int64_t n) {
   for (; i < n; i += stride) u[i] = T(0);
 }
 
-template <class T, int NM>
-hipError_t scan_nm(const Workspace& w, const Modes& md, int64_t M, int64_t N, T* u, hipStream_t s,
-                   Timeline* tl) {
-  const int64_t P = M + N;
+template <class T, int NM, int OUT>
+hipError_t scan_nm(const Workspace& w, const Modes& md, int64_t P, const T* b,
+                   const ScanOut<T>& out, hipStream_t s, Timeline* tl) {
   const dim3 grid((unsigned)w.scan_tiles);
-  hipLaunchKernelGGL((k_reduce<T, NM>), grid, dim3(kWave), 0, s, w.keys[0], w.keys[1], w.pass,
-                     (const T*)w.b, P, md, (T*)w.agg, w.tile_k);
+  hipLaunchKernelGGL((k_reduce<T, NM>), grid, dim3(kWave), 0, s, w.keys[0], w.keys[1], w.pass, b,
+                     P, md, (T*)w.agg, w.tile_k);
   tl->mark(s);
   hipLaunchKernelGGL((k_carry<T, NM>), dim3(NM), dim3(kCarryThreads), 0, s, (const T*)w.agg,
                      w.scan_tiles, (T*)w.carry);
   tl->mark(s);
-  hipLaunchKernelGGL((k_final_fast<T, NM>), grid, dim3(kScanThreads), 0, s, w.keys[0], w.keys[1],
-                     w.pass, (const T*)w.b, w.slot, M, P, md, (const T*)w.agg, (const T*)w.carry,
-                     w.tile_k, u);
-  hipLaunchKernelGGL((k_final<T, NM>), grid, dim3(kScanThreads), 0, s, w.keys[0], w.keys[1], w.pass,
-                     (const T*)w.b, w.slot, M, P, md, (const T*)w.carry, w.tile_k, u);
+  hipLaunchKernelGGL((k_final_fast<T, NM, OUT>), grid, dim3(kScanThreads), 0, s, w.keys[0],
+                     w.keys[1], w.pass, b, w.ids, P, md, (const T*)w.agg, (const T*)w.carry,
+                     w.tile_k, out);
+  hipLaunchKernelGGL((k_final<T, NM, OUT>), grid, dim3(kScanThreads), 0, s, w.keys[0], w.keys[1],
+                     w.pass, b, w.ids, P, md, (const T*)w.carry, w.tile_k, out);
   tl->mark(s);
   return hipGetLastError();
+}
+
+template <class T, int NM>
+hipError_t scan_out(const Workspace& w, const Modes& md, int64_t P, const T* b,
+                    const ScanOut<T>& out, hipStream_t s, Timeline* tl) {
+  const int kind = (out.val ? kOutVal : 0) | (out.der ? kOutDer : 0);
+  switch (kind) {
+    case kOutVal: return scan_nm<T, NM, kOutVal>(w, md, P, b, out, s, tl);
+    case kOutDer: return scan_nm<T, NM, kOutDer>(w, md, P, b, out, s, tl);
+    case kOutVal | kOutDer: return scan_nm<T, NM, kOutVal | kOutDer>(w, md, P, b, out, s, tl);
+    default: return hipSuccess;   // nothing asked for
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_gather(const uint32_t* __restrict__ ids, int64_t P,
+                                                uint32_t lo, uint32_t n, const T* __restrict__ wts,
+                                                T* __restrict__ b) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; p < P; p += stride) {
+    const uint32_t o = ids[p] - lo;
+    b[p] = o < n ? wts[o] : T(0);
+  }
+}
+
+// Partial sums of sum_i (x_i - c) dx_i + sum_j (y_j - c) dy_j in double,
+// grid-stride (fixed order for a fixed grid), one partial per block.
+template <class T>
+__global__ __launch_bounds__(256) void k_delta_part(const void* keys0, const void* keys1,
+                                                    const PassInfo* __restrict__ pass, int64_t P,
+                                                    const T* __restrict__ x,
+                                                    const T* __restrict__ dx, int64_t M,
+                                                    const T* __restrict__ y,
+                                                    const T* __restrict__ dy, int64_t N,
+                                                    double* __restrict__ part) {
+  __shared__ double wsum[256 / kWave];
+  const void* keys = pass->final_buf ? keys1 : keys0;
+  const double c = 0.5 * ((double)key_value<T>(keys, 0) + (double)key_value<T>(keys, P - 1));
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  for (int64_t i = t; i < M; i += stride) acc += ((double)x[i] - c) * (double)dx[i];
+  for (int64_t j = t; j < N; j += stride) acc += ((double)y[j] - c) * (double)dy[j];
+  for (int o = kWave / 2; o >= 1; o >>= 1) acc += shfl_xor(acc, o);
+  if (threadIdx.x % kWave == 0) wsum[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int w = 0; w < 256 / kWave; ++w) sum += wsum[w];
+    part[blockIdx.x] = sum;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kWave) void k_delta_final(const double* __restrict__ part, int nparts,
+                                                       double scale, T* __restrict__ out) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kWave) acc += part[i];
+  for (int o = kWave / 2; o >= 1; o >>= 1) acc += shfl_xor(acc, o);
+  if (threadIdx.x == 0) out[0] = (T)(scale * acc);
 }
 
 }  // namespace
 
 template <class T>
-hipError_t scan_points(const Workspace& w, const Modes& md, int64_t M, int64_t N, T* u,
-                       hipStream_t s, Timeline* tl) {
+hipError_t scan_points(const Workspace& w, const Modes& md, int64_t P, const T* b,
+                       const ScanOut<T>& out, hipStream_t s, Timeline* tl) {
   switch (md.n) {
-    case 1: return scan_nm<T, 1>(w, md, M, N, u, s, tl);
-    case 2: return scan_nm<T, 2>(w, md, M, N, u, s, tl);
-    case 3: return scan_nm<T, 3>(w, md, M, N, u, s, tl);
-    case 4: return scan_nm<T, 4>(w, md, M, N, u, s, tl);
-    case 5: return scan_nm<T, 5>(w, md, M, N, u, s, tl);
-    case 6: return scan_nm<T, 6>(w, md, M, N, u, s, tl);
-    case 7: return scan_nm<T, 7>(w, md, M, N, u, s, tl);
-    case 8: return scan_nm<T, 8>(w, md, M, N, u, s, tl);
+    case 1: return scan_out<T, 1>(w, md, P, b, out, s, tl);
+    case 2: return scan_out<T, 2>(w, md, P, b, out, s, tl);
+    case 3: return scan_out<T, 3>(w, md, P, b, out, s, tl);
+    case 4: return scan_out<T, 4>(w, md, P, b, out, s, tl);
+    case 5: return scan_out<T, 5>(w, md, P, b, out, s, tl);
+    case 6: return scan_out<T, 6>(w, md, P, b, out, s, tl);
+    case 7: return scan_out<T, 7>(w, md, P, b, out, s, tl);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <class T>
+hipError_t gather_strengths(const Workspace& w, int64_t P, uint32_t lo, uint32_t n, const T* wts,
+                            T* b, hipStream_t s) {
+  int64_t blocks = (P + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)blocks), dim3(256), 0, s, w.ids, P, lo, n, wts, b);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t delta_gradient(const Workspace& w, int64_t P, const T* x, const T* dx, int64_t M,
+                          const T* y, const T* dy, int64_t N, double delta, T* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_delta_part<T>, dim3(kRedBlocks), dim3(256), 0, s, w.keys[0], w.keys[1],
+                     w.pass, P, x, dx, M, y, dy, N, w.red);
+  hipLaunchKernelGGL(k_delta_final<T>, dim3(1), dim3(kWave), 0, s, (const double*)w.red,
+                     kRedBlocks, -0.5 / delta, out);
+  return hipGetLastError();
 }
 
 template <class T>
@@ -799,10 +907,20 @@ hipError_t fill_zero(T* u, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-template hipError_t scan_points<double>(const Workspace&, const Modes&, int64_t, int64_t, double*,
-                                        hipStream_t, Timeline*);
-template hipError_t scan_points<float>(const Workspace&, const Modes&, int64_t, int64_t, float*,
-                                       hipStream_t, Timeline*);
+template hipError_t scan_points<double>(const Workspace&, const Modes&, int64_t, const double*,
+                                        const ScanOut<double>&, hipStream_t, Timeline*);
+template hipError_t scan_points<float>(const Workspace&, const Modes&, int64_t, const float*,
+                                       const ScanOut<float>&, hipStream_t, Timeline*);
+template hipError_t gather_strengths<double>(const Workspace&, int64_t, uint32_t, uint32_t,
+                                             const double*, double*, hipStream_t);
+template hipError_t gather_strengths<float>(const Workspace&, int64_t, uint32_t, uint32_t,
+                                            const float*, float*, hipStream_t);
+template hipError_t delta_gradient<double>(const Workspace&, int64_t, const double*, const double*,
+                                           int64_t, const double*, const double*, int64_t, double,
+                                           double*, hipStream_t);
+template hipError_t delta_gradient<float>(const Workspace&, int64_t, const float*, const float*,
+                                          int64_t, const float*, const float*, int64_t, double,
+                                          float*, hipStream_t);
 template hipError_t fill_zero<double>(double*, int64_t, hipStream_t);
 template hipError_t fill_zero<float>(float*, int64_t, hipStream_t);
 

@@ -184,7 +184,7 @@ template <class T>
 __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     int d, const T* __restrict__ x, const T* __restrict__ y, const T* __restrict__ alpha, int64_t N,
     int64_t P, void* keys0, void* keys1, uint32_t* idx0, uint32_t* idx1, T* __restrict__ b_out,
-    uint32_t* __restrict__ slot_out,
+    uint32_t* __restrict__ ids_out,
     const uint32_t* __restrict__ dig_off, const PassInfo* __restrict__ pass,
     uint32_t* __restrict__ tile_ctr, uint64_t* lb_cur, uint64_t* lb_next,
     uint32_t* __restrict__ status) {
@@ -406,9 +406,9 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   for (int i = 0; i < kSortItems; ++i)
     if (base + i * kWave + lane < P && pos[i] < (uint32_t)kSortTile) sid[pos[i]] = id[i];
   __syncthreads();
-  // The last pass writes, instead of the permutation, what the scan needs:
-  // the strength of each sorted point (alpha gathered here, once) and the
-  // output slot of each target.
+  // The last pass writes the final permutation to its own array, which the
+  // scans keep using, and the strength of each sorted point (alpha gathered
+  // here, once).
   const bool last = d == pass->last_pass;
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
@@ -417,9 +417,8 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     const uint32_t out = outpos[r];
     const uint32_t id = sid[j];
     if (last) {
-      const bool src_pt = (int64_t)id < N;
-      b_out[out] = src_pt ? alpha[id] : T(0);
-      slot_out[out] = src_pt ? kNoSlot : (uint32_t)((int64_t)id - N);
+      b_out[out] = (int64_t)id < N ? alpha[id] : T(0);
+      ids_out[out] = id;
     } else {
       iout[out] = id;
     }
@@ -447,7 +446,7 @@ hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, co
   tl->mark(s);
   for (int d = 0; d < D; ++d) {
     hipLaunchKernelGGL(k_onesweep<T>, dim3((unsigned)w.sort_tiles), dim3(kSortThreads), 0, s, d, x,
-                       y, alpha, N, P, w.keys[0], w.keys[1], w.idx[0], w.idx[1], (T*)w.b, w.slot,
+                       y, alpha, N, P, w.keys[0], w.keys[1], w.idx[0], w.idx[1], (T*)w.b, w.ids,
                        w.dig_off, w.pass,
                        w.tile_ctr, w.lookback[d & 1], w.lookback[(d + 1) & 1], w.status);
     tl->mark(s);
