@@ -59,6 +59,9 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   w.agg = take((size_t)esz * kAggStride * (size_t)n_modes * (size_t)w.scan_tiles);
   w.tile_k = (int32_t*)take(sizeof(int32_t) * (size_t)w.scan_tiles);
   w.carry = take((size_t)esz * 4 * (size_t)n_modes * (size_t)w.scan_tiles);
+  const int64_t chunks = (w.scan_tiles + kWave - 1) / kWave;
+  w.chunk_agg = take((size_t)esz * 6 * (size_t)n_modes * (size_t)chunks);
+  w.chunk_carry = take((size_t)esz * 4 * (size_t)n_modes * (size_t)chunks);
   w.keys[0] = take((size_t)esz * (size_t)P);
   w.keys[1] = take((size_t)esz * (size_t)P);
   // The two permutation buffers are consecutive; after the sort they hold the

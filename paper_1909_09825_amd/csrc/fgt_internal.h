@@ -149,6 +149,8 @@ struct Workspace {
   void* agg;             // [scan_tiles][modes][kAggStride] scalars (complex A, F, G, eF, eG)
   int32_t* tile_k;       // [scan_tiles] moments used for the tile, -1 if it is too wide
   void* carry;           // [scan_tiles][modes][4] scalars: CF, CB (complex)
+  void* chunk_agg;       // [chunks][modes][6]: composed (A, F, G) of 64 consecutive tiles
+  void* chunk_carry;     // [chunks][modes][4]: CF, CB entering each chunk
   size_t zero_bytes;     // bytes from `status` that the first kernel clears
   int64_t sort_tiles, scan_tiles;
   size_t total;

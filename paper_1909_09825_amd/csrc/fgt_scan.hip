@@ -29,7 +29,7 @@
 //              about the tile centre c:  sum_q b_q exp(+-tau (z_q - c)) =
 //              sum_m (+-tau)^m mu_m / m!,  mu_m = sum_q b_q (z_q - c)^m;
 //              otherwise from the recurrences themselves.
-//   k_carry    per mode: exclusive prefix of F and suffix of G over tiles.
+//   k_carry_* per mode: exclusive prefix of F and suffix of G over tiles.
 //   k_final    per tile: chunk -> wave -> tile scans of both recurrences with
 //              the carries, sweeps, mode reduction, scatter to the outputs.
 #include "fgt_internal.h"
@@ -272,36 +272,32 @@ __global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void*
 }
 
 // ---------------------------------------------------------------------------
-// k_carry: carries over tiles for mode blockIdx.x.  CF[t] = forward value
-// entering tile t from the left (h+ at the point before it), CB[t] =
-// backward value entering from the right (h- at its last point).
+// Carries over tiles, for every scan q (one per mode; q = channel * modes +
+// mode when two strength channels share the sweeps).  CF[t] = forward value
+// entering tile t from the left (h+ at the point before it), CB[t] = backward
+// value entering from the right (h- at its last point).  Three levels so that
+// the whole chip takes part: tiles are grouped in chunks of 64 (one wave per
+// chunk and scan),
+//   k_carry_up    the composed map of each chunk,
+//   k_carry_top   per scan, the values entering each chunk (sequential runs
+//                 per thread, then a block scan),
+//   k_carry_down  per chunk, the values entering each of its tiles.
 // ---------------------------------------------------------------------------
-template <class T, int NM>
-__global__ __launch_bounds__(kCarryThreads) void k_carry(const T* __restrict__ agg, int64_t tiles,
-                                                         T* __restrict__ carry) {
-  constexpr int W = kCarryThreads / kWave;
-  __shared__ Seg<T> wf[W], wb[W];
-  const int k = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int lane = tid % kWave;
-  const int wave = tid / kWave;
-  const int64_t per = (tiles + kCarryThreads - 1) / kCarryThreads;
-  const int64_t a0 = (int64_t)tid * per;
-  const int64_t a1 = a0 + per < tiles ? a0 + per : tiles;
+template <class T>
+__device__ __forceinline__ Seg<T> load_seg(const T* __restrict__ p) {
+  Seg<T> s;
+  s.a = {p[0], p[1]};
+  s.f = {p[2], p[3]};
+  s.g = {p[4], p[5]};
+  return s;
+}
 
-  auto tile_seg = [&](int64_t t) {
-    const T* p = agg + ((size_t)t * NM + k) * kAggStride;
-    Seg<T> s;
-    s.a = {p[0], p[1]};
-    s.f = {p[2], p[3]};
-    s.g = {p[4], p[5]};
-    return s;
-  };
-  Seg<T> mine = seg_identity<T>();
-#pragma unroll 8
-  for (int64_t t = a0; t < a1; ++t) mine = compose(mine, tile_seg(t));
-
-  Seg<T> pf = mine, sb = mine;
+// Inclusive prefix (pf: A, F) and suffix (sb: A, G) of the lanes' maps.
+template <class T>
+__device__ __forceinline__ void wave_scans(const Seg<T>& s, int lane, Seg<T>& pf, Seg<T>& sb) {
+  pf = s;
+  sb = s;
+#pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     Seg<T> l, r;
     l.a.re = shfl_up(pf.a.re, o); l.a.im = shfl_up(pf.a.im, o);
@@ -317,6 +313,47 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(const T* __restrict__ a
       sb.a = cmul(sb.a, r.a);
     }
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(kWave) void k_carry_up(const T* __restrict__ agg, int64_t tiles, int nq,
+                                                    T* __restrict__ chunk_agg) {
+  const int lane = threadIdx.x;
+  const int q = blockIdx.y;
+  const int64_t chunk = blockIdx.x;
+  const int64_t t = chunk * kWave + lane;
+  const Seg<T> s = t < tiles ? load_seg(agg + ((size_t)t * nq + q) * kAggStride) : seg_identity<T>();
+  Seg<T> pf, sb;
+  wave_scans(s, lane, pf, sb);
+  T* o = chunk_agg + ((size_t)chunk * nq + q) * 6;
+  if (lane == kWave - 1) {
+    o[0] = pf.a.re; o[1] = pf.a.im;
+    o[2] = pf.f.re; o[3] = pf.f.im;
+  }
+  if (lane == 0) {
+    o[4] = sb.g.re; o[5] = sb.g.im;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kCarryThreads) void k_carry_top(const T* __restrict__ chunk_agg,
+                                                             int64_t chunks, int nq,
+                                                             T* __restrict__ chunk_carry) {
+  constexpr int W = kCarryThreads / kWave;
+  __shared__ Seg<T> wf[W], wb[W];
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave;
+  const int wave = tid / kWave;
+  const int64_t per = (chunks + kCarryThreads - 1) / kCarryThreads;
+  const int64_t a0 = (int64_t)tid * per;
+  const int64_t a1 = a0 + per < chunks ? a0 + per : chunks;
+  auto seg = [&](int64_t c) { return load_seg(chunk_agg + ((size_t)c * nq + q) * 6); };
+
+  Seg<T> mine = seg_identity<T>();
+  for (int64_t c = a0; c < a1; ++c) mine = compose(mine, seg(c));
+  Seg<T> pf, sb;
+  wave_scans(mine, lane, pf, sb);
   if (lane == kWave - 1) wf[wave] = pf;
   if (lane == 0) wb[wave] = sb;
   __syncthreads();
@@ -333,21 +370,50 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(const T* __restrict__ a
   if (lane > 0) cf = cfma(xl.a, cf, xl.f);
   if (lane < kWave - 1) cb = cfma(xr.a, cb, xr.g);
 
-#pragma unroll 8
-  for (int64_t t = a0; t < a1; ++t) {
-    T* o = carry + ((size_t)t * NM + k) * 4;
+  for (int64_t c = a0; c < a1; ++c) {
+    T* o = chunk_carry + ((size_t)c * nq + q) * 4;
     o[0] = cf.re;
     o[1] = cf.im;
-    const Seg<T> s = tile_seg(t);
+    const Seg<T> s = seg(c);
     cf = cfma(s.a, cf, s.f);
   }
-#pragma unroll 8
-  for (int64_t t = a1 - 1; t >= a0; --t) {
-    T* o = carry + ((size_t)t * NM + k) * 4;
+  for (int64_t c = a1 - 1; c >= a0; --c) {
+    T* o = chunk_carry + ((size_t)c * nq + q) * 4;
     o[2] = cb.re;
     o[3] = cb.im;
-    const Seg<T> s = tile_seg(t);
+    const Seg<T> s = seg(c);
     cb = cfma(s.a, cb, s.g);
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kWave) void k_carry_down(const T* __restrict__ agg, int64_t tiles,
+                                                      int nq, const T* __restrict__ chunk_carry,
+                                                      T* __restrict__ carry) {
+  const int lane = threadIdx.x;
+  const int q = blockIdx.y;
+  const int64_t chunk = blockIdx.x;
+  const int64_t t = chunk * kWave + lane;
+  const Seg<T> s = t < tiles ? load_seg(agg + ((size_t)t * nq + q) * kAggStride) : seg_identity<T>();
+  Seg<T> pf, sb;
+  wave_scans(s, lane, pf, sb);
+  const T* cc = chunk_carry + ((size_t)chunk * nq + q) * 4;
+  C<T> cf = {cc[0], cc[1]};
+  C<T> cb = {cc[2], cc[3]};
+  // exclusive: the tiles before / after this one inside the chunk
+  Seg<T> xl, xr;
+  xl.a.re = shfl_up(pf.a.re, 1); xl.a.im = shfl_up(pf.a.im, 1);
+  xl.f.re = shfl_up(pf.f.re, 1); xl.f.im = shfl_up(pf.f.im, 1);
+  xr.a.re = shfl_down(sb.a.re, 1); xr.a.im = shfl_down(sb.a.im, 1);
+  xr.g.re = shfl_down(sb.g.re, 1); xr.g.im = shfl_down(sb.g.im, 1);
+  if (lane > 0) cf = cfma(xl.a, cf, xl.f);
+  if (lane < kWave - 1) cb = cfma(xr.a, cb, xr.g);
+  if (t < tiles) {
+    T* o = carry + ((size_t)t * nq + q) * 4;
+    o[0] = cf.re;
+    o[1] = cf.im;
+    o[2] = cb.re;
+    o[3] = cb.im;
   }
 }
 
@@ -781,6 +847,18 @@ __global__ void k_fill_zero(T* __restrict__ u, int64_t n) {
   for (; i < n; i += stride) u[i] = T(0);
 }
 
+template <class T>
+hipError_t carry_tiles(const Workspace& w, int nq, hipStream_t s) {
+  const int64_t chunks = (w.scan_tiles + kWave - 1) / kWave;
+  hipLaunchKernelGGL(k_carry_up<T>, dim3((unsigned)chunks, (unsigned)nq), dim3(kWave), 0, s,
+                     (const T*)w.agg, w.scan_tiles, nq, (T*)w.chunk_agg);
+  hipLaunchKernelGGL(k_carry_top<T>, dim3((unsigned)nq), dim3(kCarryThreads), 0, s,
+                     (const T*)w.chunk_agg, chunks, nq, (T*)w.chunk_carry);
+  hipLaunchKernelGGL(k_carry_down<T>, dim3((unsigned)chunks, (unsigned)nq), dim3(kWave), 0, s,
+                     (const T*)w.agg, w.scan_tiles, nq, (const T*)w.chunk_carry, (T*)w.carry);
+  return hipGetLastError();
+}
+
 template <class T, int NM, int OUT>
 hipError_t scan_nm(const Workspace& w, const Modes& md, int64_t P, const T* b,
                    const ScanOut<T>& out, hipStream_t s, Timeline* tl) {
@@ -788,8 +866,7 @@ hipError_t scan_nm(const Workspace& w, const Modes& md, int64_t P, const T* b,
   hipLaunchKernelGGL((k_reduce<T, NM>), grid, dim3(kWave), 0, s, w.keys[0], w.keys[1], w.pass, b,
                      P, md, (T*)w.agg, w.tile_k);
   tl->mark(s);
-  hipLaunchKernelGGL((k_carry<T, NM>), dim3(NM), dim3(kCarryThreads), 0, s, (const T*)w.agg,
-                     w.scan_tiles, (T*)w.carry);
+  (void)carry_tiles<T>(w, NM, s);
   tl->mark(s);
   hipLaunchKernelGGL((k_final_fast<T, NM, OUT>), grid, dim3(kScanThreads), 0, s, w.keys[0],
                      w.keys[1], w.pass, b, w.ids, P, md, (const T*)w.agg, (const T*)w.carry,
