@@ -156,6 +156,63 @@ int fgt_backward(fgt_plan_t plan, const void* x, int64_t M, const void* y, const
                  int flags, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Batched transforms.  B independent transforms in CSR layout: transform b has
+ * targets x[x_off[b] .. x_off[b+1]), sources y[y_off[b] .. y_off[b+1]), its own
+ * delta[b] > 0, and R strength columns: alpha is [y_off[B]][R] row-major and
+ * u is [x_off[B]][R] row-major, u[i][r] = sum_j S_b(x_i - y_j) alpha[j][r] over
+ * the sources of the transform that target i belongs to.  All transforms share
+ * the SOE table chosen for `digits`; since its nodes scale as 1/sqrt(delta)
+ * (1.3), transform b runs on coordinates scaled by 1/sqrt(delta_b).  Only FP64
+ * is served (FGT_EUNSUPPORTED for FGT_F32).
+ *
+ * fgt_batch_plan -- validate the layout and build the per-transform tables.
+ *   delta, x_off, y_off  HOST arrays ([B], [B+1], [B+1]); offsets start at 0 and
+ *                        do not decrease.  1 <= R <= 64.  x_off[B] + y_off[B]
+ *                        must be below 2^31 - 1.
+ *   out                  receives the plan (device tables allocated here, with
+ *                        hipMalloc and synchronous copies; release with
+ *                        fgt_batch_destroy once no fgt_batch_eval using it is pending).
+ * Errors: FGT_EINVAL (null pointers, offsets, deltas, R, digits), FGT_EUNSUPPORTED,
+ * FGT_EDEVICE.
+ */
+typedef struct fgt_batch_s* fgt_batch_t;
+int fgt_batch_plan(int64_t B, const double* delta, int digits, int dtype, const int64_t* x_off,
+                   const int64_t* y_off, int R, fgt_batch_t* out);
+
+/* Device workspace bytes for fgt_batch_eval (0 for a null plan). */
+size_t fgt_batch_workspace_size(fgt_batch_t plan);
+
+/* Modes, stated bound E_n and total merged points of a batch plan (host pointers, any null). */
+int fgt_batch_info(fgt_batch_t plan, int* n_modes, double* err_bound, int64_t* total_points);
+
+/*
+ * fgt_batch_eval -- all B transforms, enqueued on `stream` as a fixed sequence
+ * of kernels: no allocation, no host synchronisation and no memset, so the
+ * call may be captured into a HIP graph and replayed.  x, y, alpha, u, ws are
+ * device pointers (ws 256-byte aligned, fgt_batch_workspace_size bytes, not
+ * shared with a concurrent call).  Non-finite scaled coordinates are reported by
+ * fgt_last_device_status(ws, stream).
+ * Errors: FGT_EINVAL (null pointers, workspace), FGT_EDEVICE.
+ */
+int fgt_batch_eval(fgt_batch_t plan, const void* x, const void* y, const void* alpha, void* u,
+                   void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Release a batch plan.  Accepts null. */
+void fgt_batch_destroy(fgt_batch_t plan);
+
+/*
+ * fgt_eval_batched -- one-shot form: plan, evaluate, wait for `stream`, release.
+ * Arguments as for fgt_batch_plan and fgt_batch_eval; the workspace size comes
+ * from fgt_eval_batched_workspace_size (0 on invalid arguments).  Unlike the
+ * other entry points it allocates (the plan's tables) and synchronises.
+ */
+size_t fgt_eval_batched_workspace_size(int64_t B, const int64_t* x_off, const int64_t* y_off,
+                                       int R, int digits);
+int fgt_eval_batched(int64_t B, const double* delta, int digits, int dtype, const int64_t* x_off,
+                     const int64_t* y_off, const void* x, const void* y, const void* alpha, int R,
+                     void* u, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * fgt_last_device_status -- synchronise `stream`, then read and clear the
  * status word that the last fgt_eval on workspace `ws` left there.
  * Returns FGT_OK, FGT_ENONFINITE, or FGT_EINVAL / FGT_EDEVICE.

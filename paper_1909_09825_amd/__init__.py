@@ -8,10 +8,12 @@ of include/fgt.h.
 """
 from ._lib import (FGT_EDEVICE, FGT_EINVAL, FGT_ENONFINITE, FGT_EUNSUPPORTED, FGT_F32, FGT_F64,
                    FGT_OK, FGT_SORTED, FGTError, LIB_PATH)
-from .api import (GaussTransform, Plan, backward, eval, eval_sorted, gauss_transform,
-                  last_device_status, max_digits, plan, profile_begin, profile_end, workspace)
+from .api import (BatchPlan, GaussTransform, Plan, backward, batch_plan, batch_workspace, eval,
+                  eval_batch, eval_sorted, gauss_transform, last_device_status, max_digits, plan,
+                  profile_begin, profile_end, workspace)
 
 __all__ = ["Plan", "plan", "eval", "eval_sorted", "backward", "GaussTransform", "gauss_transform",
+           "BatchPlan", "batch_plan", "eval_batch", "batch_workspace",
            "workspace", "last_device_status", "max_digits", "FGTError",
            "FGT_OK", "FGT_EINVAL", "FGT_EUNSUPPORTED", "FGT_ENONFINITE", "FGT_EDEVICE",
            "FGT_F64", "FGT_F32", "FGT_SORTED", "LIB_PATH", "profile_begin", "profile_end"]

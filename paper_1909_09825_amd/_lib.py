@@ -51,6 +51,22 @@ def load() -> ctypes.CDLL:
     lib.fgt_backward.argtypes = [vp, vp, c_i64, vp, vp, c_i64, vp, vp, vp, vp, vp, c_int, vp,
                                  ctypes.c_size_t, vp]
     lib.fgt_backward.restype = c_int
+    i64p = ctypes.POINTER(c_i64)
+    lib.fgt_batch_plan.argtypes = [c_i64, dp, c_int, c_int, i64p, i64p, c_int, ctypes.POINTER(vp)]
+    lib.fgt_batch_plan.restype = c_int
+    lib.fgt_batch_workspace_size.argtypes = [vp]
+    lib.fgt_batch_workspace_size.restype = ctypes.c_size_t
+    lib.fgt_batch_info.argtypes = [vp, ip, dp, i64p]
+    lib.fgt_batch_info.restype = c_int
+    lib.fgt_batch_eval.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.fgt_batch_eval.restype = c_int
+    lib.fgt_batch_destroy.argtypes = [vp]
+    lib.fgt_batch_destroy.restype = None
+    lib.fgt_eval_batched_workspace_size.argtypes = [c_i64, i64p, i64p, c_int, c_int]
+    lib.fgt_eval_batched_workspace_size.restype = ctypes.c_size_t
+    lib.fgt_eval_batched.argtypes = [c_i64, dp, c_int, c_int, i64p, i64p, vp, vp, vp, c_int, vp, vp,
+                                     ctypes.c_size_t, vp]
+    lib.fgt_eval_batched.restype = c_int
     lib.fgt_last_device_status.argtypes = [vp, vp]
     lib.fgt_last_device_status.restype = c_int
     lib.fgt_strerror.argtypes = [c_int]

@@ -237,6 +237,94 @@ def gauss_transform(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor, delta
     return GaussTransform.apply(x, y, alpha, delta, digits)
 
 
+class BatchPlan:
+    """B independent transforms in CSR layout (host offsets), one delta each, R columns.
+
+    Transform b: targets x[x_off[b]:x_off[b+1]], sources y[y_off[b]:y_off[b+1]],
+    strengths alpha[y_off[b]:y_off[b+1], :R]; FP64 only.
+    """
+
+    def __init__(self, delta, digits: int, x_off, y_off, R: int = 1,
+                 dtype: torch.dtype = torch.float64):
+        if dtype not in _DTYPES:
+            raise ValueError(f"dtype must be float64 or float32, got {dtype}")
+        lib = _lib.load()
+        self._delta = np.ascontiguousarray(np.asarray(delta, dtype=np.float64))
+        self._xo = np.ascontiguousarray(np.asarray(x_off, dtype=np.int64))
+        self._yo = np.ascontiguousarray(np.asarray(y_off, dtype=np.int64))
+        B = self._delta.shape[0]
+        if self._xo.shape != (B + 1,) or self._yo.shape != (B + 1,):
+            raise ValueError("x_off and y_off must have B + 1 entries")
+        h = ctypes.c_void_p()
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        rc = lib.fgt_batch_plan(B, self._delta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                int(digits), _DTYPES[dtype], self._xo.ctypes.data_as(i64p),
+                                self._yo.ctypes.data_as(i64p), int(R), ctypes.byref(h))
+        if rc == _lib.FGT_EINVAL:
+            raise ValueError(f"fgt_batch_plan: {_lib.strerror(rc)}")
+        check(rc, "fgt_batch_plan")
+        self._h, self._lib = h, lib
+        self.B, self.R, self.digits, self.dtype = B, int(R), int(digits), dtype
+        self.M, self.N = int(self._xo[-1]), int(self._yo[-1])
+        n, e, tp = ctypes.c_int(), ctypes.c_double(), ctypes.c_int64()
+        check(lib.fgt_batch_info(h, ctypes.byref(n), ctypes.byref(e), ctypes.byref(tp)),
+              "fgt_batch_info")
+        self.n_modes, self.err_bound, self.total_points = n.value, e.value, tp.value
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def workspace_size(self) -> int:
+        return int(self._lib.fgt_batch_workspace_size(self._h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.fgt_batch_destroy(h)
+            self._h = None
+
+
+def batch_plan(delta, digits: int, x_off, y_off, R: int = 1) -> BatchPlan:
+    return BatchPlan(delta, digits, x_off, y_off, R)
+
+
+def eval_batch(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor, bp: BatchPlan,
+               out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """u[sum M, R] for every transform of the batch plan, on the current stream."""
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise ValueError("x must be a CUDA (HIP) tensor")
+    dev = x.device
+    x = _vec(x, "x", bp.dtype, dev)
+    y = _vec(y, "y", bp.dtype, dev)
+    if x.shape[0] != bp.M or y.shape[0] != bp.N:
+        raise ValueError(f"x and y must have {bp.M} and {bp.N} entries")
+    if alpha.dim() == 1 and bp.R == 1:
+        alpha = alpha.reshape(-1, 1)
+    if (alpha.dim() != 2 or alpha.shape != (bp.N, bp.R) or alpha.dtype != bp.dtype
+            or alpha.device != dev):
+        raise ValueError(f"alpha must be a {bp.dtype} tensor of shape ({bp.N}, {bp.R}) on {dev}")
+    alpha = alpha.contiguous()
+    if out is None:
+        out = torch.empty((bp.M, bp.R), dtype=bp.dtype, device=dev)
+    elif out.shape != (bp.M, bp.R) or not out.is_contiguous() or out.dtype != bp.dtype:
+        raise ValueError("out must be a contiguous tensor of shape (M, R)")
+    need = bp.workspace_size()
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    elif ws.numel() * ws.element_size() < need or not ws.is_contiguous() or ws.device != dev:
+        raise ValueError(f"workspace must be a contiguous {dev} tensor of >= {need} bytes")
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = bp._lib.fgt_batch_eval(bp.handle, x.data_ptr(), y.data_ptr(), alpha.data_ptr(),
+                                out.data_ptr(), ws.data_ptr(), need, stream)
+    check(rc, "fgt_batch_eval")
+    return out
+
+
+def batch_workspace(bp: BatchPlan, device) -> torch.Tensor:
+    return torch.empty(max(bp.workspace_size(), 1), dtype=torch.uint8, device=device)
+
+
 def last_device_status(ws: torch.Tensor) -> int:
     """Synchronise the current stream; return and clear the device status of `ws` (0 = ok)."""
     stream = torch.cuda.current_stream(ws.device).cuda_stream

@@ -76,6 +76,84 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   return w;
 }
 
+const SoeTable* choose_table(int digits) {
+  const double target = pow(10.0, -digits);
+  const SoeTable* tab = nullptr;
+  for (int i = 0; i < FGT_SOE_NUM_TABLES; ++i) {
+    if (kSoeTables[i].err_bound <= target && (!tab || kSoeTables[i].n_modes < tab->n_modes))
+      tab = &kSoeTables[i];
+  }
+  return tab;
+}
+
+int max_digits(int dtype) {
+  if (dtype == FGT_F64) return max_digits_f64();
+  if (dtype == FGT_F32) return 6;
+  return 0;
+}
+
+void make_modes(const SoeTable* tab, double delta, int dtype, Modes* m) {
+  memset(m, 0, sizeof(*m));
+  m->n = tab->n_modes;
+  const double rs = 1.0 / sqrt(delta);
+  m->tau_abs_max = 0.0;
+  for (int k = 0; k < tab->n_modes; ++k) {
+    m->tau_re[k] = tab->tau0_re[k] * rs;
+    m->tau_im[k] = tab->tau0_im[k] * rs;
+    m->om_re[k] = tab->om_re[k];
+    m->om_im[k] = tab->om_im[k];
+    m->tau_abs[k] = hypot(m->tau_re[k], m->tau_im[k]);
+    m->dom_re[k] = -(m->tau_re[k] * tab->om_re[k] - m->tau_im[k] * tab->om_im[k]);
+    m->dom_im[k] = -(m->tau_re[k] * tab->om_im[k] + m->tau_im[k] * tab->om_re[k]);
+    if (m->tau_abs[k] > m->tau_abs_max) m->tau_abs_max = m->tau_abs[k];
+  }
+  // Sort resolution.  Two points closer than w = s_w sqrt(delta) may be left in
+  // either order.  If a source at y and a target at x swap places, x - y
+  // changes sign and the recurrences evaluate S at -|x - y| instead of
+  // +|x - y| (continued through the same exponentials); with s = |x - y| /
+  // sqrt(delta) the change is |Re sum omega (e^{tau0 s} - e^{-tau0 s})| <=
+  // 2 |Re sum omega tau0| s + (1/3) sum |omega| |tau0|^3 s^3 cosh(max|tau0| s).
+  // s_w makes this at most 1e-6 E_n, so the result stays within
+  // (1 + 1e-6) E_n sum|alpha| of the Gauss transform.
+  {
+    double slope = 0.0, c3 = 0.0, tmax = 0.0;
+    for (int k = 0; k < tab->n_modes; ++k) {
+      slope += tab->om_re[k] * tab->tau0_re[k] - tab->om_im[k] * tab->tau0_im[k];
+      const double ta = hypot(tab->tau0_re[k], tab->tau0_im[k]);
+      c3 += hypot(tab->om_re[k], tab->om_im[k]) * ta * ta * ta;
+      if (ta > tmax) tmax = ta;
+    }
+    slope = fabs(slope);
+    const double target = 1e-6 * tab->err_bound;
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 200; ++it) {
+      const double s = 0.5 * (lo + hi);
+      const double b = 2.0 * slope * s + c3 * s * s * s * cosh(tmax * s) / 3.0;
+      if (b <= target) lo = s; else hi = s;
+    }
+    m->key_width = lo * sqrt(delta);
+  }
+  for (int k = 0; k < tab->n_modes; ++k) {
+    double cr = 1.0, ci = 0.0;
+    for (int j = 0; j <= kTaylorMax; ++j) {
+      m->coef_re[k][j] = cr;
+      m->coef_im[k][j] = ci;
+      const double nr = (-m->tau_re[k] * cr + m->tau_im[k] * ci) / (j + 1);
+      const double ni = (-m->tau_re[k] * ci - m->tau_im[k] * cr) / (j + 1);
+      cr = nr;
+      ci = ni;
+    }
+  }
+  // Taylor thresholds for the element type's unit roundoff.
+  const double unit = dtype == FGT_F64 ? ldexp(1.0, -53) : ldexp(1.0, -24);
+  double fact = 1.0;
+  m->taylor_thr[0] = 0.0;
+  for (int d = 1; d <= kTaylorMax; ++d) {
+    fact *= (d + 1);   // (d+1)!
+    m->taylor_thr[d] = pow(unit * fact, 1.0 / (d + 1));
+  }
+}
+
 // Benchmark timing state (see fgt_profile_begin).
 struct Profiler {
   bool on = false;
@@ -176,11 +254,7 @@ const char* fgt_strerror(int status) {
   }
 }
 
-int fgt_max_digits(int dtype) {
-  if (dtype == FGT_F64) return fgt::max_digits_f64();
-  if (dtype == FGT_F32) return 6;
-  return 0;
-}
+int fgt_max_digits(int dtype) { return fgt::max_digits(dtype); }
 
 int fgt_plan(double delta, int digits, int dtype, fgt_plan_t* out) {
   if (!out) return FGT_EINVAL;
@@ -189,78 +263,14 @@ int fgt_plan(double delta, int digits, int dtype, fgt_plan_t* out) {
   if (dtype != FGT_F64 && dtype != FGT_F32) return FGT_EINVAL;
   if (digits < 1 || digits > fgt::max_digits_f64()) return FGT_EINVAL;
   if (digits > fgt_max_digits(dtype)) return FGT_EUNSUPPORTED;
-  const double target = pow(10.0, -digits);
-  const fgt::SoeTable* tab = nullptr;
-  for (int i = 0; i < FGT_SOE_NUM_TABLES; ++i) {
-    if (fgt::kSoeTables[i].err_bound <= target &&
-        (!tab || fgt::kSoeTables[i].n_modes < tab->n_modes))
-      tab = &fgt::kSoeTables[i];
-  }
+  const fgt::SoeTable* tab = fgt::choose_table(digits);
   if (!tab) return FGT_EUNSUPPORTED;
   fgt_plan_s* p = new (std::nothrow) fgt_plan_s;
   if (!p) return FGT_EINVAL;
   p->dtype = dtype;
   p->delta = delta;
   p->table = tab;
-  memset(&p->modes, 0, sizeof(p->modes));
-  p->modes.n = tab->n_modes;
-  const double rs = 1.0 / sqrt(delta);
-  p->modes.tau_abs_max = 0.0;
-  for (int k = 0; k < tab->n_modes; ++k) {
-    p->modes.tau_re[k] = tab->tau0_re[k] * rs;
-    p->modes.tau_im[k] = tab->tau0_im[k] * rs;
-    p->modes.om_re[k] = tab->om_re[k];
-    p->modes.om_im[k] = tab->om_im[k];
-    p->modes.tau_abs[k] = hypot(p->modes.tau_re[k], p->modes.tau_im[k]);
-    p->modes.dom_re[k] = -(p->modes.tau_re[k] * tab->om_re[k] - p->modes.tau_im[k] * tab->om_im[k]);
-    p->modes.dom_im[k] = -(p->modes.tau_re[k] * tab->om_im[k] + p->modes.tau_im[k] * tab->om_re[k]);
-    if (p->modes.tau_abs[k] > p->modes.tau_abs_max) p->modes.tau_abs_max = p->modes.tau_abs[k];
-  }
-  // Sort resolution.  Two points closer than w = s_w sqrt(delta) may be left in
-  // either order.  If a source at y and a target at x swap places, x - y
-  // changes sign and the recurrences evaluate S at -|x - y| instead of
-  // +|x - y| (continued through the same exponentials); with s = |x - y| /
-  // sqrt(delta) the change is |Re sum omega (e^{tau0 s} - e^{-tau0 s})| <=
-  // 2 |Re sum omega tau0| s + (1/3) sum |omega| |tau0|^3 s^3 cosh(max|tau0| s).
-  // s_w makes this at most 1e-6 E_n, so the result stays within
-  // (1 + 1e-6) E_n sum|alpha| of the Gauss transform.
-  {
-    double slope = 0.0, c3 = 0.0, tmax = 0.0;
-    for (int k = 0; k < tab->n_modes; ++k) {
-      slope += tab->om_re[k] * tab->tau0_re[k] - tab->om_im[k] * tab->tau0_im[k];
-      const double ta = hypot(tab->tau0_re[k], tab->tau0_im[k]);
-      c3 += hypot(tab->om_re[k], tab->om_im[k]) * ta * ta * ta;
-      if (ta > tmax) tmax = ta;
-    }
-    slope = fabs(slope);
-    const double target = 1e-6 * tab->err_bound;
-    double lo = 0.0, hi = 1.0;
-    for (int it = 0; it < 200; ++it) {
-      const double s = 0.5 * (lo + hi);
-      const double b = 2.0 * slope * s + c3 * s * s * s * cosh(tmax * s) / 3.0;
-      if (b <= target) lo = s; else hi = s;
-    }
-    p->modes.key_width = lo * sqrt(delta);
-  }
-  for (int k = 0; k < tab->n_modes; ++k) {
-    double cr = 1.0, ci = 0.0;
-    for (int m = 0; m <= fgt::kTaylorMax; ++m) {
-      p->modes.coef_re[k][m] = cr;
-      p->modes.coef_im[k][m] = ci;
-      const double nr = (-p->modes.tau_re[k] * cr + p->modes.tau_im[k] * ci) / (m + 1);
-      const double ni = (-p->modes.tau_re[k] * ci - p->modes.tau_im[k] * cr) / (m + 1);
-      cr = nr;
-      ci = ni;
-    }
-  }
-  // Taylor thresholds for the element type's unit roundoff.
-  const double unit = dtype == FGT_F64 ? ldexp(1.0, -53) : ldexp(1.0, -24);
-  double fact = 1.0;
-  p->modes.taylor_thr[0] = 0.0;
-  for (int d = 1; d <= fgt::kTaylorMax; ++d) {
-    fact *= (d + 1);   // (d+1)!
-    p->modes.taylor_thr[d] = pow(unit * fact, 1.0 / (d + 1));
-  }
+  fgt::make_modes(tab, delta, dtype, &p->modes);
   *out = p;
   return FGT_OK;
 }
@@ -386,6 +396,212 @@ int fgt_backward(fgt_plan_t plan, const void* x, int64_t M, const void* y, const
                      : fgt::backward<float>(plan, w, x, M, y, alpha, N, g, dalpha, dx, dy, ddelta,
                                            sort, stream);
   return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+}
+
+}  // extern "C"
+
+struct fgt_batch_s {
+  int digits;
+  fgt::Modes modes;        // the table at delta = 1
+  double s_allow;          // sort resolution in scaled coordinates
+  fgt::BatchDims dims;
+  int max_nb_log2;
+  fgt::SegInfo* d_seg;
+  fgt::ChunkInfo* d_chunks;
+  fgt::BucketInfo* d_buckets;
+  int64_t* d_ne_base;
+  double* d_ne_scale;
+};
+
+namespace fgt {
+namespace {
+
+void batch_free(fgt_batch_s* b) {
+  if (!b) return;
+  if (b->d_seg) (void)hipFree(b->d_seg);
+  if (b->d_chunks) (void)hipFree(b->d_chunks);
+  if (b->d_buckets) (void)hipFree(b->d_buckets);
+  if (b->d_ne_base) (void)hipFree(b->d_ne_base);
+  if (b->d_ne_scale) (void)hipFree(b->d_ne_scale);
+  delete b;
+}
+
+// Host part of a batch plan: validation, per-transform tables, sizes.
+int batch_tables(int64_t B, const double* delta, const int64_t* x_off, const int64_t* y_off, int R,
+                 std::vector<SegInfo>& seg, std::vector<ChunkInfo>& chunks,
+                 std::vector<BucketInfo>& buckets, std::vector<int64_t>& ne_base,
+                 std::vector<double>& ne_scale, BatchDims& d, int& max_nb_log2) {
+  if (B < 0 || R < 1 || R > 64) return FGT_EINVAL;
+  if (B > 0 && (!delta || !x_off || !y_off)) return FGT_EINVAL;
+  if (B > (int64_t(1) << 30)) return FGT_EINVAL;
+  if (B > 0 && (x_off[0] != 0 || y_off[0] != 0)) return FGT_EINVAL;
+  memset(&d, 0, sizeof(d));
+  d.B = B;
+  d.R = R;
+  max_nb_log2 = 0;
+  int64_t base = 0, chunk0 = 0, bucket0 = 0, cnt0 = 0;
+  seg.resize((size_t)B);
+  for (int64_t b = 0; b < B; ++b) {
+    const int64_t M = x_off[b + 1] - x_off[b];
+    const int64_t N = y_off[b + 1] - y_off[b];
+    if (M < 0 || N < 0) return FGT_EINVAL;
+    if (!(delta[b] > 0.0) || !isfinite(delta[b])) return FGT_EINVAL;
+    const int64_t Pb = M + N;
+    SegInfo& sg = seg[(size_t)b];
+    sg.x_off = x_off[b];
+    sg.y_off = y_off[b];
+    sg.M = M;
+    sg.N = N;
+    sg.base = base;
+    sg.scale = 1.0 / sqrt(delta[b]);
+    if (!isfinite(sg.scale)) return FGT_EINVAL;
+    sg.n_chunks = (int32_t)((Pb + kBChunk - 1) / kBChunk);
+    int lg = 0;
+    while (lg < kMaxBucketLog2 && ((int64_t)kBucketTarget << lg) < Pb) ++lg;
+    sg.nb_log2 = lg;
+    if (lg > max_nb_log2) max_nb_log2 = lg;
+    sg.chunk0 = chunk0;
+    sg.bucket0 = bucket0;
+    sg.cnt0 = cnt0;
+    for (int32_t c = 0; c < sg.n_chunks; ++c) chunks.push_back(ChunkInfo{(int32_t)b, 0, (int64_t)c * kBChunk});
+    for (int32_t k = 0; k < (1 << lg); ++k) buckets.push_back(BucketInfo{(int32_t)b, k});
+    chunk0 += sg.n_chunks;
+    bucket0 += 1 << lg;
+    cnt0 += (int64_t)(1 << lg) * sg.n_chunks;
+    if (Pb > 0) {
+      ne_base.push_back(base);
+      ne_scale.push_back(sg.scale);
+    }
+    base += Pb;
+  }
+  d.SN = B > 0 ? y_off[B] : 0;
+  d.SM = B > 0 ? x_off[B] : 0;
+  d.P = base;
+  if (d.SN + d.SM > (int64_t)0x7ffffffe) return FGT_EINVAL;
+  d.n_chunks = chunk0;
+  d.n_buckets = bucket0;
+  d.n_counts = cnt0;
+  d.K = (int64_t)ne_base.size();
+  d.tiles = (d.P + kBTile - 1) / kBTile;
+  if (d.tiles < 1) d.tiles = 1;
+  return FGT_OK;
+}
+
+template <class V>
+hipError_t upload(const std::vector<V>& v, V** out) {
+  *out = nullptr;
+  const size_t bytes = sizeof(V) * (v.empty() ? 1 : v.size());
+  hipError_t e = hipMalloc((void**)out, bytes);
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(*out, v.data(), sizeof(V) * v.size(), hipMemcpyHostToDevice);
+  return e;
+}
+
+}  // namespace
+}  // namespace fgt
+
+extern "C" {
+
+int fgt_batch_plan(int64_t B, const double* delta, int digits, int dtype, const int64_t* x_off,
+                   const int64_t* y_off, int R, fgt_batch_t* out) {
+  if (!out) return FGT_EINVAL;
+  *out = nullptr;
+  if (dtype != FGT_F64 && dtype != FGT_F32) return FGT_EINVAL;
+  if (digits < 1 || digits > fgt::max_digits_f64()) return FGT_EINVAL;
+  if (dtype != FGT_F64) return FGT_EUNSUPPORTED;
+  const fgt::SoeTable* tab = fgt::choose_table(digits);
+  if (!tab) return FGT_EUNSUPPORTED;
+  std::vector<fgt::SegInfo> seg;
+  std::vector<fgt::ChunkInfo> chunks;
+  std::vector<fgt::BucketInfo> buckets;
+  std::vector<int64_t> ne_base;
+  std::vector<double> ne_scale;
+  fgt::BatchDims d;
+  int max_lg = 0;
+  int rc = fgt::batch_tables(B, delta, x_off, y_off, R, seg, chunks, buckets, ne_base, ne_scale, d,
+                             max_lg);
+  if (rc != FGT_OK) return rc;
+  fgt_batch_s* b = new (std::nothrow) fgt_batch_s;
+  if (!b) return FGT_EINVAL;
+  memset(b, 0, sizeof(*b));
+  b->digits = digits;
+  fgt::make_modes(tab, 1.0, FGT_F64, &b->modes);
+  b->s_allow = b->modes.key_width;
+  d.n_modes = b->modes.n;
+  b->dims = d;
+  b->max_nb_log2 = max_lg;
+  if (fgt::upload(seg, &b->d_seg) != hipSuccess || fgt::upload(chunks, &b->d_chunks) != hipSuccess ||
+      fgt::upload(buckets, &b->d_buckets) != hipSuccess ||
+      fgt::upload(ne_base, &b->d_ne_base) != hipSuccess ||
+      fgt::upload(ne_scale, &b->d_ne_scale) != hipSuccess) {
+    fgt::batch_free(b);
+    return FGT_EDEVICE;
+  }
+  *out = b;
+  return FGT_OK;
+}
+
+size_t fgt_batch_workspace_size(fgt_batch_t plan) {
+  if (!plan) return 0;
+  return fgt::batch_layout(nullptr, plan->dims).total;
+}
+
+int fgt_batch_info(fgt_batch_t plan, int* n_modes, double* err_bound, int64_t* total_points) {
+  if (!plan) return FGT_EINVAL;
+  if (n_modes) *n_modes = plan->modes.n;
+  if (err_bound) *err_bound = fgt::choose_table(plan->digits)->err_bound;
+  if (total_points) *total_points = plan->dims.P;
+  return FGT_OK;
+}
+
+int fgt_batch_eval(fgt_batch_t plan, const void* x, const void* y, const void* alpha, void* u,
+                   void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!plan) return FGT_EINVAL;
+  const fgt::BatchDims& d = plan->dims;
+  if ((d.SM > 0 && (!x || !u)) || (d.SN > 0 && (!y || !alpha)) || !ws) return FGT_EINVAL;
+  if (((uintptr_t)ws & 255u) != 0) return FGT_EINVAL;
+  const fgt::BatchWork w = fgt::batch_layout(ws, d);
+  if (ws_bytes < w.total) return FGT_EINVAL;
+  hipError_t e = fgt::batch_eval_launch(d, plan->modes, plan->s_allow, plan->d_seg,
+                                        plan->d_chunks, plan->d_buckets, plan->d_ne_base,
+                                        plan->d_ne_scale, plan->max_nb_log2,
+                                        (const double*)x, (const double*)y, (const double*)alpha,
+                                        (double*)u, w, stream);
+  return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+}
+
+void fgt_batch_destroy(fgt_batch_t plan) { fgt::batch_free(plan); }
+
+size_t fgt_eval_batched_workspace_size(int64_t B, const int64_t* x_off, const int64_t* y_off, int R,
+                                       int digits) {
+  const fgt::SoeTable* tab = (digits >= 1 && digits <= fgt::max_digits_f64()) ? fgt::choose_table(digits) : nullptr;
+  if (!tab || B < 0 || (B > 0 && (!x_off || !y_off))) return 0;
+  std::vector<double> ones((size_t)(B > 0 ? B : 1), 1.0);
+  std::vector<fgt::SegInfo> seg;
+  std::vector<fgt::ChunkInfo> chunks;
+  std::vector<fgt::BucketInfo> buckets;
+  std::vector<int64_t> ne_base;
+  std::vector<double> ne_scale;
+  fgt::BatchDims d;
+  int max_lg = 0;
+  if (fgt::batch_tables(B, ones.data(), x_off, y_off, R, seg, chunks, buckets, ne_base, ne_scale, d,
+                        max_lg) != FGT_OK)
+    return 0;
+  d.n_modes = tab->n_modes;
+  return fgt::batch_layout(nullptr, d).total;
+}
+
+int fgt_eval_batched(int64_t B, const double* delta, int digits, int dtype, const int64_t* x_off,
+                     const int64_t* y_off, const void* x, const void* y, const void* alpha, int R,
+                     void* u, void* ws, size_t ws_bytes, hipStream_t stream) {
+  fgt_batch_t plan = nullptr;
+  int rc = fgt_batch_plan(B, delta, digits, dtype, x_off, y_off, R, &plan);
+  if (rc != FGT_OK) return rc;
+  rc = fgt_batch_eval(plan, x, y, alpha, u, ws, ws_bytes, stream);
+  // The plan's tables are in use by the enqueued kernels until the stream drains.
+  if (hipStreamSynchronize(stream) != hipSuccess && rc == FGT_OK) rc = FGT_EDEVICE;
+  fgt_batch_destroy(plan);
+  return rc;
 }
 
 int fgt_profile_begin(void) {

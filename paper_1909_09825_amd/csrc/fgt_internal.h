@@ -166,6 +166,13 @@ struct Timeline {
   }
 };
 
+// Smallest shipped table with E_n <= 10^-digits (null if none).
+const SoeTable* choose_table(int digits);
+// Largest digits served for an element type.
+int max_digits(int dtype);
+// Scale a table to delta and fill the kernel constants for the element type.
+void make_modes(const SoeTable* tab, double delta, int dtype, Modes* m);
+
 // Layout for P points, element size `esz` (8 or 4), n_modes modes.  With
 // base == nullptr only sizes are computed.
 Workspace layout(void* base, int64_t P, int esz, int n_modes);
@@ -192,5 +199,88 @@ hipError_t delta_gradient(const Workspace& w, int64_t P, const T* x, const T* dx
                           const T* y, const T* dy, int64_t N, double delta, T* out, hipStream_t s);
 template <class T>
 hipError_t fill_zero(T* u, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched transforms (B independent transforms in CSR layout, R strength
+// columns).  Coordinates of transform b are scaled by s_b = 1/sqrt(delta_b),
+// so one table at delta = 1 serves every transform.
+// ---------------------------------------------------------------------------
+// Sort: each transform's merged points [sources; targets] are split by the top
+// bits of a quantised key into buckets of about kBucketTarget points (stable
+// counting per chunk of kBChunk points), then every bucket is radix-sorted in
+// LDS (kBucketMax points at most; larger buckets take a slower block-global path).
+constexpr int kBChunk = 4096;
+constexpr int kBucketTarget = 2048;
+constexpr int kBucketMax = 4096;
+constexpr int kBSortThreads = 512;
+constexpr int kBSortItems = kBucketMax / kBSortThreads;   // 8
+constexpr int kMaxBucketLog2 = 12;
+// Scan: tiles of kBTile sorted points; a wave holds 4 chunks x 16 columns,
+// a lane runs kBChunkPts consecutive points of one column.
+constexpr int kBCols = 16;
+constexpr int kBThreads = 512;
+constexpr int kBChunkPts = 16;
+constexpr int kBTile = (kBThreads / kBCols) * kBChunkPts;   // 512
+// Bit of a sorted id that marks the first point of a transform.
+constexpr uint32_t kSegStart = 0x80000000u;
+
+struct SegInfo {
+  int64_t x_off, y_off;   // first target row, first source row
+  int64_t M, N;           // targets, sources
+  int64_t base;           // first sorted position of the transform
+  int64_t chunk0;         // first chunk of the transform
+  int64_t bucket0;        // first bucket of the transform
+  int64_t cnt0;           // first entry of its [bucket][chunk] count table
+  double scale;           // 1 / sqrt(delta_b)
+  int32_t n_chunks;
+  int32_t nb_log2;        // log2 of its bucket count
+};
+struct ChunkInfo {
+  int32_t seg;
+  int32_t pad;
+  int64_t start;          // first merged index of the chunk inside its transform
+};
+struct BucketInfo {
+  int32_t seg;
+  int32_t idx;
+};
+
+struct BatchWork {
+  uint32_t* status;       // [64] at offset 0
+  double* lo;             // [B] smallest scaled coordinate per transform
+  double* hi;             // [B] largest
+  uint32_t* counts;       // [sum n_chunks * nb] bucket-major per transform
+  uint32_t* offs;         // [same] exclusive offsets
+  uint32_t* bstart;       // [sum nb] bucket start inside its transform
+  uint32_t* bsize;        // [sum nb]
+  uint32_t* ids_tmp;      // [P] merged indices after the bucket split
+  uint64_t* qbuf[2];      // [P] keys of the block-global path
+  uint32_t* ibuf[2];      // [P]
+  double* zs;             // [P] sorted coordinates
+  uint32_t* ids;          // [P] sorted codes: source row, or SN + target row; kSegStart flag
+  double* tile_a;         // [tiles][modes][2]
+  double* tile_fg;        // [tiles][modes][R][4]
+  double* chunk_agg;      // [chunks][modes * R][6]
+  double* chunk_carry;    // [chunks][modes * R][4]
+  double* carry;          // [tiles][modes * R][4]
+  size_t total;
+};
+
+struct BatchDims {
+  int64_t B, P, SN, SM, n_chunks, n_buckets, n_counts, tiles;
+  int64_t K;              // transforms with at least one point
+  int R, n_modes;
+};
+
+BatchWork batch_layout(void* base, const BatchDims& d);
+
+// ne_base / ne_scale: first sorted position and 1/sqrt(delta) of each transform
+// with at least one point, in order.
+hipError_t batch_eval_launch(const BatchDims& d, const Modes& md, double s_allow,
+                             const SegInfo* seg, const ChunkInfo* chunks,
+                             const BucketInfo* buckets, const int64_t* ne_base,
+                             const double* ne_scale, int max_nb_log2, const double* x,
+                             const double* y, const double* alpha, double* u,
+                             const BatchWork& w, hipStream_t s);
 
 }  // namespace fgt

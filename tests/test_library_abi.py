@@ -139,3 +139,52 @@ def test_backward_and_eval_sorted_validation():
     assert lib.fgt_eval_sorted(h, 4, 4, d, d, d, ws_ok - 1, None) == fgt.FGT_EINVAL
     assert lib.fgt_eval_sorted(h, 0, 4, d, d, d, ws_ok, None) == fgt.FGT_OK
     lib.fgt_plan_destroy(h)
+
+
+def _i64p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def test_batch_plan_validation():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    delta = np.array([1e-3, 1e-4, 1e-2])
+    xo = np.array([0, 10, 10, 25], np.int64)
+    yo = np.array([0, 5, 17, 17], np.int64)
+    bad = [
+        (3, delta, 6, fgt.FGT_F64, xo, yo, 0),                                  # R = 0
+        (3, delta, 6, fgt.FGT_F64, xo, yo, 65),                                 # R too large
+        (3, delta, 0, fgt.FGT_F64, xo, yo, 4),                                  # digits
+        (3, np.array([1e-3, -1.0, 1e-2]), 6, fgt.FGT_F64, xo, yo, 4),           # delta <= 0
+        (3, np.array([1e-3, np.nan, 1e-2]), 6, fgt.FGT_F64, xo, yo, 4),         # delta NaN
+        (3, delta, 6, fgt.FGT_F64, np.array([1, 10, 10, 25], np.int64), yo, 4),  # x_off[0] != 0
+        (3, delta, 6, fgt.FGT_F64, np.array([0, 10, 9, 25], np.int64), yo, 4),   # decreasing
+        (3, delta, 6, 7, xo, yo, 4),                                             # dtype
+        (-1, delta, 6, fgt.FGT_F64, xo, yo, 4),                                  # B < 0
+    ]
+    for B, d, dig, dt, x_off, y_off, R in bad:
+        assert lib.fgt_batch_plan(B, _dp(d), dig, dt, _i64p(x_off), _i64p(y_off), R,
+                                  ctypes.byref(h)) == fgt.FGT_EINVAL
+    assert lib.fgt_batch_plan(3, _dp(delta), 6, fgt.FGT_F32, _i64p(xo), _i64p(yo), 4,
+                              ctypes.byref(h)) == fgt.FGT_EUNSUPPORTED
+    assert lib.fgt_batch_plan(3, None, 6, fgt.FGT_F64, _i64p(xo), _i64p(yo), 4,
+                              ctypes.byref(h)) == fgt.FGT_EINVAL
+    assert lib.fgt_batch_eval(None, None, None, None, None, None, 0, None) == fgt.FGT_EINVAL
+    assert lib.fgt_batch_workspace_size(None) == 0
+    lib.fgt_batch_destroy(None)
+
+
+def test_batch_workspace_size_grows_with_points_and_columns():
+    lib = _lib.load()
+    xo = np.array([0, 1000, 1000, 5000], np.int64)
+    yo = np.array([0, 300, 9000, 9000], np.int64)
+    s1 = lib.fgt_eval_batched_workspace_size(3, _i64p(xo), _i64p(yo), 1, 6)
+    s16 = lib.fgt_eval_batched_workspace_size(3, _i64p(xo), _i64p(yo), 16, 6)
+    big = lib.fgt_eval_batched_workspace_size(3, _i64p(xo * 4), _i64p(yo * 4), 16, 6)
+    assert 0 < s1 < s16 < big
+    assert lib.fgt_eval_batched_workspace_size(3, _i64p(xo), _i64p(yo), 0, 6) == 0
+    assert lib.fgt_eval_batched_workspace_size(3, _i64p(xo), _i64p(yo), 4, 0) == 0
