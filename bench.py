@@ -9,6 +9,10 @@ delta = 1e-4, 6 digits (4 modes), FP64, with inputs resident in HBM.
 Prints ONE JSON line.  `value` is (M+N) * modes / s.  `fwd_bwd` times, on the
 same inputs, the forward followed by the adjoint (fgt_backward on the sorted
 workspace: dL/dalpha, dL/dx, dL/dy and dL/ddelta for L = g . u, g ~ N(0,1)).
+`batched` times fgt_batch_eval on 4096 transforms (N_b, M_b log-uniform in
+[256, 65536], delta_b log-uniform in [1e-6, 1e-2], 16 columns, 6 digits),
+eagerly and as a replayed HIP graph, next to a loop of fgt_eval calls (one per
+transform and column) timed on 32 of the transforms and scaled to 4096.
 `roofline` describes
 the kernel with the largest share of the step, timed with HIP events recorded
 by the library on its own stream during the timed steps; `cpu_baseline` is
@@ -45,6 +49,7 @@ def parse():
                     help="CPU oracle timed on the first 2^k targets and sources")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the fwd+bwd timing")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched timing")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one plain device copy of this many bytes (counter calibration)")
     return ap.parse_args()
@@ -81,6 +86,81 @@ def cpu_baseline(x, y, a, delta, digits, n_modes, k):
         "sample": (f"first 2^{k} targets and 2^{k} sources of the same inputs, {digits} digits "
                    f"({n_modes} modes): O2 SOE recurrence in C (qsort, then one sweep per mode and "
                    f"direction, OpenMP over the {2 * n_modes} sweeps), {dt:.2f} s wall"),
+    }
+
+
+def bench_batched(args, fgt, W, torch, np, dev):
+    bt = W.batched()
+    B, R = len(bt.delta), bt.alpha.shape[1]
+    bp = fgt.batch_plan(bt.delta, bt.digits, bt.x_off, bt.y_off, R)
+    X = torch.from_numpy(bt.x).to(dev)
+    Y = torch.from_numpy(bt.y).to(dev)
+    A = torch.from_numpy(bt.alpha).to(dev)
+    U = torch.empty((bp.M, R), dtype=torch.float64, device=dev)
+    ws = fgt.batch_workspace(bp, dev)
+    for _ in range(args.warmup):
+        fgt.eval_batch(X, Y, A, bp, out=U, ws=ws)
+    torch.cuda.synchronize()
+    if fgt.last_device_status(ws) != fgt.FGT_OK:
+        raise RuntimeError("device status after batched warmup")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fgt.eval_batch(X, Y, A, bp, out=U, ws=ws)
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / args.steps
+    # the same launch sequence captured once and replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fgt.eval_batch(X, Y, A, bp, out=U, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fgt.eval_batch(X, Y, A, bp, out=U, ws=ws)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / args.steps
+    # loop of single-transform calls on 32 transforms, all columns
+    picks = np.random.default_rng(4).choice(B, 32, replace=False)
+    calls = []
+    for b in picks:
+        xs, xe, ys, ye = (int(bt.x_off[b]), int(bt.x_off[b + 1]), int(bt.y_off[b]),
+                          int(bt.y_off[b + 1]))
+        p = fgt.plan(float(bt.delta[b]), bt.digits)
+        wsb = fgt.workspace(p, xe - xs, ye - ys, dev)
+        cols = [A[ys:ye, r].contiguous() for r in range(R)]
+        calls.append((p, X[xs:xe], Y[ys:ye], cols, U[xs:xe, 0].clone(), wsb))
+    for p, xb, yb, cols, ub, wsb in calls:
+        fgt.eval(xb, yb, cols[0], p, out=ub, ws=wsb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, xb, yb, cols, ub, wsb in calls:
+        for c in cols:
+            fgt.eval(xb, yb, c, p, out=ub, ws=wsb)
+    torch.cuda.synchronize()
+    ms_loop32 = (time.perf_counter() - t0) * 1e3
+    pts32 = sum(int(c[1].shape[0] + c[2].shape[0]) for c in calls)
+    ms_loop = ms_loop32 * bp.total_points / pts32
+    ms = min(ms_eager, ms_graph)
+    return {
+        "workload": (f"{B} transforms, N_b and M_b log-uniform in [256, 65536], delta_b "
+                     f"log-uniform in [1e-6, 1e-2], points uniform on [0,1), alpha [N][{R}] ~ N(0,1), "
+                     f"{bt.digits} digits ({bp.n_modes} modes), FP64"),
+        "total_points": bp.total_points,
+        "ms_per_batch_eager": round(ms_eager, 4),
+        "ms_per_batch_graph": round(ms_graph, 4),
+        "transforms_per_s": B / (ms * 1e-3),
+        "column_transforms_per_s": B * R / (ms * 1e-3),
+        "value": bp.total_points * bp.n_modes * R / (ms * 1e-3),
+        "unit": "point-mode-columns/s",
+        "loop_of_fgt_eval_ms": round(ms_loop, 2),
+        "loop_sample": (f"fgt_eval once per column on 32 sampled transforms ({pts32} points), "
+                        f"{ms_loop32:.1f} ms, scaled by total points"),
+        "speedup_vs_loop": round(ms_loop / ms, 1),
     }
 
 
@@ -235,6 +315,8 @@ def main():
             "ratio_to_fwd": round(ms_fb / ms_step, 4),
             "step": "fgt_eval + fgt_backward(FGT_SORTED) giving dL/dalpha, dL/dx, dL/dy, dL/ddelta",
         }
+    if not args.no_batched and not args.fp32:
+        out["batched"] = bench_batched(args, fgt, W, torch, np, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr.x, pr.y, pr.alpha, args.delta, args.digits, n_modes,
                                            min(args.cpu_sample_log2n, args.log2n))

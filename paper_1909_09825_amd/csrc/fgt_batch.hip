@@ -523,6 +523,10 @@ __global__ __launch_bounds__(kBSortThreads) void k_bucket_sort(
 // consecutive points of the tile, c is the column inside the column group
 // blockIdx.y.
 // ---------------------------------------------------------------------------
+// Position of tile point e in the exponential table: one spare entry per
+// chunk staggers the chunks read together by a wave across LDS banks.
+__device__ __forceinline__ int expad(int e) { return e + e / kBChunkPts; }
+
 template <int NM, bool REDUCE>
 __global__ __launch_bounds__(kBThreads) void k_bscan(
     const double* __restrict__ zs, const uint32_t* __restrict__ ids, int64_t P, int64_t SN,
@@ -537,7 +541,7 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
   __shared__ uint32_t s_wflag[kWaves];
   __shared__ double s_z[kBTile + 1];
   __shared__ uint32_t s_id[kBTile];
-  __shared__ double s_ex[2 * kBTile];
+  __shared__ double s_ex[2 * (kBTile + kBTile / kBChunkPts)];   // padded per chunk: no bank conflicts
   __shared__ double s_wt[kWaves][kBCols][6];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int cl = lane % kBCols;
@@ -595,7 +599,6 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
 
 #pragma unroll 1
   for (int k = 0; k < NM; ++k) {
-    const double tr = md.tau_re[k], ti = md.tau_im[k];
     // Mode exponentials of the tile's gaps, 0 at the first point of a transform.
     {
       constexpr int kPer = kBTile / kBThreads;
@@ -617,18 +620,30 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
       for (int d = kTaylorMax; d >= 1; --d)
         if (rr <= md.taylor_thr[d]) D = d;
       const double dz_lim = md.taylor_thr[kTaylorMax] / md.tau_abs[k];
+      // A gap beyond the Taylor range is halved k times into it, its
+      // exponential taken there and squared k times
+      // (exp(-tau dz) = exp(-tau dz / 2^k)^(2^k)): the relative error grows to
+      // about 2^k u, but |exp(-tau dz)| = exp(-Re(tau) dz) falls faster, so the
+      // absolute error stays at the rounding level.
 #pragma unroll
       for (int q = 0; q < kPer; ++q) {
-        C<double> ex = {0.0, 0.0};
-        for (int m = D; m >= 0; --m) {
-          ex.re = fma(ex.re, dz[q], md.coef_re[k][m]);
-          ex.im = fma(ex.im, dz[q], md.coef_im[k][m]);
+        double d = dz[q];
+        int halvings = 0;
+        while (fabs(d) > dz_lim && halvings < 1100) {
+          d *= 0.5;
+          ++halvings;
         }
-        if (fabs(dz[q]) > dz_lim) ex = exp_neg_general<double>(tr, ti, dz[q]);
+        const int Dq = halvings ? kTaylorMax : D;
+        C<double> ex = {0.0, 0.0};
+        for (int m = Dq; m >= 0; --m) {
+          ex.re = fma(ex.re, d, md.coef_re[k][m]);
+          ex.im = fma(ex.im, d, md.coef_im[k][m]);
+        }
+        for (int h = 0; h < halvings; ++h) ex = cmul(ex, ex);
         if (cut[q]) ex = {0.0, 0.0};
         const int e = tid + q * kBThreads;
-        s_ex[2 * e] = ex.re;
-        s_ex[2 * e + 1] = ex.im;
+        s_ex[2 * expad(e)] = ex.re;
+        s_ex[2 * expad(e) + 1] = ex.im;
       }
     }
     __syncthreads();
@@ -640,7 +655,7 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
 #pragma unroll
       for (int j = 0; j < kBChunkPts; ++j) {
         const int e = chunk * kBChunkPts + j;
-        const C<double> ex = {s_ex[2 * e], s_ex[2 * e + 1]};
+        const C<double> ex = {s_ex[2 * expad(e)], s_ex[2 * expad(e) + 1]};
         a = cmul(a, ex);
         f = cfma(ex, f, C<double>{b[j], 0.0});
         g.re = fma(b[j], a.re, g.re);
@@ -724,7 +739,7 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
 #pragma unroll
       for (int j = 0; j < kBChunkPts; ++j) {
         const int e = chunk * kBChunkPts + j;
-        const C<double> ex = {s_ex[2 * e], s_ex[2 * e + 1]};
+        const C<double> ex = {s_ex[2 * expad(e)], s_ex[2 * expad(e) + 1]};
         hh = cfma(ex, hh, C<double>{b[j], 0.0});
         acc[j] = fma(om_re, hh.re, fma(-om_im, hh.im, acc[j]));
       }
@@ -732,7 +747,7 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
 #pragma unroll
       for (int j = kBChunkPts - 1; j >= 0; --j) {
         const int e = chunk * kBChunkPts + j;
-        const C<double> ex = {s_ex[2 * e], s_ex[2 * e + 1]};
+        const C<double> ex = {s_ex[2 * expad(e)], s_ex[2 * expad(e) + 1]};
         acc[j] = fma(om_re, g.re, fma(-om_im, g.im, acc[j]));
         g = cmul(ex, cadd(g, C<double>{b[j], 0.0}));
       }
