@@ -143,13 +143,17 @@ int fgt_eval_sorted(fgt_plan_t plan, int64_t M, int64_t N, const void* alpha, vo
  * (the last from u(c x, c y; c^2 delta) = u(x, y; delta), which S obeys exactly
  * because its nodes scale as 1/sqrt(delta)).  All are device arrays of the plan's
  * type: g[M], dalpha[N], dx[M], dy[N], ddelta a single element.  Any output may
- * be null to skip it, except that ddelta needs dx (if M > 0) and dy (if N > 0).
- *   flags  0 or FGT_SORTED.  With FGT_SORTED the sort held in `ws` (see
- *          fgt_eval_sorted) is reused and x, y are read only for ddelta;
- *          otherwise the points are sorted first.
+ * be null to skip it.  The gradients come from one adjoint pass over the sorted
+ * points in which the strengths alpha (for dL/dx) and g (for dL/dalpha, dL/dy)
+ * share every mode exponential.
+ *   flags  0 or FGT_SORTED.  With FGT_SORTED, `ws` must hold the state left by
+ *          the last fgt_eval or fgt_eval_sorted with this plan and these
+ *          points: its sort and its strengths, which are used in place of
+ *          `alpha` (x, y and alpha are then not read and may be null).
+ *          Without it the points are sorted first and alpha is read.
  *   ws     as for fgt_eval; the call leaves the sorted state in it.
  * M == 0 or N == 0 writes zeros to every requested output.
- * Errors: as fgt_eval, plus FGT_EINVAL for unknown flags or ddelta without dx, dy.
+ * Errors: as fgt_eval, plus FGT_EINVAL for unknown flags.
  */
 int fgt_backward(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha,
                  int64_t N, const void* g, void* dalpha, void* dx, void* dy, void* ddelta,

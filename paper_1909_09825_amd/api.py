@@ -163,9 +163,9 @@ def backward(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor, g: torch.Ten
              dx: bool = True, dy: bool = True, ddelta: bool = True):
     """Gradients of L = sum_i g_i u_i: (dL/dalpha, dL/dx, dL/dy, dL/ddelta), None where not asked.
 
-    With sorted=True, `ws` must hold the sort of (x, y) left by eval/backward
-    with the same plan.  dL/ddelta is a 0-dim tensor; asking for it computes
-    dL/dx and dL/dy as well.
+    With sorted=True, `ws` must hold the state left by the last eval or
+    eval_sorted with this plan and these points (its sort and its strengths,
+    which stand for `alpha`).  dL/ddelta is a 0-dim tensor.
     """
     if not isinstance(x, torch.Tensor) or not x.is_cuda:
         raise ValueError("x must be a CUDA (HIP) tensor")
@@ -182,10 +182,9 @@ def backward(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor, g: torch.Ten
             raise ValueError("sorted=True needs the workspace that holds the sort")
         ws = workspace(p, M, N, dev)
     need = _check_ws(p, ws, M, N, dev)
-    want_dx, want_dy = dx or ddelta, dy or ddelta
     o_da = torch.empty(N, dtype=p.dtype, device=dev) if dalpha else None
-    o_dx = torch.empty(M, dtype=p.dtype, device=dev) if want_dx else None
-    o_dy = torch.empty(N, dtype=p.dtype, device=dev) if want_dy else None
+    o_dx = torch.empty(M, dtype=p.dtype, device=dev) if dx else None
+    o_dy = torch.empty(N, dtype=p.dtype, device=dev) if dy else None
     o_dd = torch.empty((), dtype=p.dtype, device=dev) if ddelta else None
     ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
     stream = torch.cuda.current_stream(dev).cuda_stream
@@ -193,7 +192,7 @@ def backward(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor, g: torch.Ten
                              g.data_ptr(), ptr(o_da), ptr(o_dx), ptr(o_dy), ptr(o_dd),
                              _lib.FGT_SORTED if sorted else 0, ws.data_ptr(), need, stream)
     check(rc, "fgt_backward")
-    return o_da, (o_dx if dx else None), (o_dy if dy else None), o_dd
+    return o_da, o_dx, o_dy, o_dd
 
 
 class GaussTransform(torch.autograd.Function):

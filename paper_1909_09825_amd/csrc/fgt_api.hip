@@ -56,12 +56,15 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   w.lookback[1] = (uint64_t*)take(sizeof(uint64_t) * (size_t)w.sort_tiles * kRadix);
   w.dig_off = (uint32_t*)take(sizeof(uint32_t) * digits * kRadix);
   w.pass = (PassInfo*)take(sizeof(PassInfo));
-  w.agg = take((size_t)esz * kAggStride * (size_t)n_modes * (size_t)w.scan_tiles);
+  // Scan state for up to 2 x n_modes scans (the adjoint runs two strength channels).
+  const size_t nq = 2 * (size_t)n_modes;
+  w.agg = take((size_t)esz * kAggStride * nq * (size_t)w.scan_tiles);
   w.tile_k = (int32_t*)take(sizeof(int32_t) * (size_t)w.scan_tiles);
-  w.carry = take((size_t)esz * 4 * (size_t)n_modes * (size_t)w.scan_tiles);
+  w.carry = take((size_t)esz * 4 * nq * (size_t)w.scan_tiles);
   const int64_t chunks = (w.scan_tiles + kWave - 1) / kWave;
-  w.chunk_agg = take((size_t)esz * 6 * (size_t)n_modes * (size_t)chunks);
-  w.chunk_carry = take((size_t)esz * 4 * (size_t)n_modes * (size_t)chunks);
+  w.chunk_agg = take((size_t)esz * 6 * nq * (size_t)chunks);
+  w.chunk_carry = take((size_t)esz * 4 * nq * (size_t)chunks);
+  w.tile_part = (double*)take(sizeof(double) * (size_t)w.scan_tiles);
   w.keys[0] = take((size_t)esz * (size_t)P);
   w.keys[1] = take((size_t)esz * (size_t)P);
   // The two permutation buffers are consecutive; after the sort they hold the
@@ -71,7 +74,6 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   w.bt = (void*)w.idx[0];
   w.b = take((size_t)esz * (size_t)P);
   w.ids = (uint32_t*)take(sizeof(uint32_t) * (size_t)P);
-  w.red = (double*)take(sizeof(double) * kRedBlocks);
   w.total = off;
   return w;
 }
@@ -196,44 +198,20 @@ hipError_t forward(const fgt_plan_s* plan, const Workspace& w, const void* x, in
   return scan_points<T>(w, plan->modes, P, (const T*)w.b, out, s, tl);
 }
 
-// Gradients of L = sum_i g_i u_i (see fgt_backward).
+// Gradients of L = sum_i g_i u_i (see fgt_backward): sort if asked, then the
+// one adjoint pass over the sorted points.
 template <class T>
 hipError_t backward(const fgt_plan_s* plan, const Workspace& w, const void* x, int64_t M,
                     const void* y, const void* alpha, int64_t N, const void* g, void* dalpha,
                     void* dx, void* dy, void* ddelta, bool sort, hipStream_t s) {
-  const int64_t P = M + N;
-  Timeline none;
-  hipError_t e = hipSuccess;
   if (sort) {
-    e = sort_points<T>(w, (const T*)x, M, (const T*)y, (const T*)alpha, N, plan->modes.key_width,
-                       s, &none);
-  } else if (dx) {
-    e = gather_strengths<T>(w, P, 0u, (uint32_t)N, (const T*)alpha, (T*)w.b, s);
-  }
-  if (e != hipSuccess) return e;
-  if (dx) {
-    // dL/dx_i = g_i sum_j alpha_j S'(x_i - y_j): sources alpha, outputs at the targets.
-    const ScanOut<T> out{nullptr, (T*)dx, (const T*)g, (uint32_t)N, (uint32_t)M};
-    e = scan_points<T>(w, plan->modes, P, (const T*)w.b, out, s, &none);
+    Timeline none;
+    const hipError_t e = sort_points<T>(w, (const T*)x, M, (const T*)y, (const T*)alpha, N,
+                                        plan->modes.key_width, s, &none);
     if (e != hipSuccess) return e;
   }
-  if (dalpha || dy) {
-    // Transposed: strengths g at the targets, outputs at the sources.
-    //   dL/dalpha_j = sum_i g_i S(y_j - x_i),  dL/dy_j = alpha_j sum_i g_i S'(y_j - x_i).
-    e = gather_strengths<T>(w, P, (uint32_t)N, (uint32_t)M, (const T*)g, (T*)w.bt, s);
-    if (e != hipSuccess) return e;
-    const ScanOut<T> out{(T*)dalpha, (T*)dy, (const T*)alpha, 0u, (uint32_t)N};
-    e = scan_points<T>(w, plan->modes, P, (const T*)w.bt, out, s, &none);
-    if (e != hipSuccess) return e;
-  }
-  if (ddelta) {
-    // u(c x, c y; c^2 delta) = u(x, y; delta) gives
-    //   dL/ddelta = -(sum_i x_i dL/dx_i + sum_j y_j dL/dy_j) / (2 delta),
-    // and translation invariance lets the coordinates be taken about any centre.
-    e = delta_gradient<T>(w, P, (const T*)x, (const T*)dx, M, (const T*)y, (const T*)dy, N,
-                          plan->delta, (T*)ddelta, s);
-  }
-  return e;
+  return adjoint_points<T>(w, plan->modes, M, N, (const T*)g, (T*)dx, (T*)dalpha, (T*)dy,
+                           (T*)ddelta, plan->delta, s);
 }
 
 }  // namespace
@@ -369,7 +347,6 @@ int fgt_backward(fgt_plan_t plan, const void* x, int64_t M, const void* y, const
   if (!plan || M < 0 || N < 0) return FGT_EINVAL;
   if (M + N >= (int64_t(1) << 32)) return FGT_EINVAL;
   if (flags & ~FGT_SORTED) return FGT_EINVAL;
-  if (ddelta && ((M > 0 && !dx) || (N > 0 && !dy))) return FGT_EINVAL;
   const bool f64 = plan->dtype == FGT_F64;
   auto zero = [&](void* p, int64_t n) -> hipError_t {
     if (!p || n == 0) return hipSuccess;
@@ -385,9 +362,8 @@ int fgt_backward(fgt_plan_t plan, const void* x, int64_t M, const void* y, const
     return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
   }
   if (!dalpha && !dx && !dy && !ddelta) return FGT_OK;
-  if (!g || !alpha || !ws) return FGT_EINVAL;
   const bool sort = !(flags & FGT_SORTED);
-  if ((sort || ddelta) && (!x || !y)) return FGT_EINVAL;
+  if (!g || !ws || (sort && (!x || !y || !alpha))) return FGT_EINVAL;
   if (((uintptr_t)ws & 255u) != 0) return FGT_EINVAL;
   const fgt::Workspace w = fgt::layout(ws, M + N, f64 ? 8 : 4, plan->modes.n);
   if (ws_bytes < w.total) return FGT_EINVAL;

@@ -82,8 +82,6 @@ constexpr int kCarryThreads = 1024;
 constexpr int kAggStride = 10;
 // Tiles whose moment count is at most this take the fast final kernel.
 constexpr int kFastMoments = 12;
-// Blocks of the delta-gradient reduction.
-constexpr int kRedBlocks = 512;
 
 
 template <class T> struct KeyOf;
@@ -138,7 +136,7 @@ struct Workspace {
   uint32_t* ids;         // [P] merged index of each sorted point: j < N source j, else target j - N
   void* bt;              // [P] strengths of the transposed transform (g_i at targets, 0 at
                          //     sources); shares the permutation buffers, which are dead after the sort
-  double* red;           // [kRedBlocks] partial sums of the delta-gradient reduction
+  double* tile_part;     // [scan_tiles] per-tile parts of the delta-gradient sum
   uint32_t* status;      // [1] at offset 0, zeroed per call
   unsigned long long* maxabs;  // [1] largest |coordinate| as ordered bits, zeroed per call
   uint32_t* hist;        // [digits][256], zeroed per call
@@ -146,7 +144,8 @@ struct Workspace {
   uint64_t* lookback[2]; // [sort_tiles][256]; [0] zeroed per call, each pass clears the other
   uint32_t* dig_off;     // [digits][256]
   PassInfo* pass;
-  void* agg;             // [scan_tiles][modes][kAggStride] scalars (complex A, F, G, eF, eG)
+  void* agg;             // [scan_tiles][scans][kAggStride] scalars (complex A, F, G, eF, eG);
+                         // scans = modes for the transform, 2 x modes for its adjoint
   int32_t* tile_k;       // [scan_tiles] moments used for the tile, -1 if it is too wide
   void* carry;           // [scan_tiles][modes][4] scalars: CF, CB (complex)
   void* chunk_agg;       // [chunks][modes][6]: composed (A, F, G) of 64 consecutive tiles
@@ -192,11 +191,11 @@ hipError_t scan_points(const Workspace& w, const Modes& m, int64_t P, const T* b
 template <class T>
 hipError_t gather_strengths(const Workspace& w, int64_t P, uint32_t lo, uint32_t n, const T* wts,
                             T* b, hipStream_t s);
-// *out = -(sum_i (x_i - c) dx_i + sum_j (y_j - c) dy_j) / (2 delta), c the midpoint of
-// the sorted coordinates.
+// Gradients of L = sum_i g_i u_i from the sorted state of the last forward
+// call (keys, ids, and the forward strengths b); any output may be null.
 template <class T>
-hipError_t delta_gradient(const Workspace& w, int64_t P, const T* x, const T* dx, int64_t M,
-                          const T* y, const T* dy, int64_t N, double delta, T* out, hipStream_t s);
+hipError_t adjoint_points(const Workspace& w, const Modes& md, int64_t M, int64_t N, const T* g,
+                          T* dx, T* dalpha, T* dy, T* ddelta, double delta, hipStream_t s);
 template <class T>
 hipError_t fill_zero(T* u, int64_t n, hipStream_t s);
 

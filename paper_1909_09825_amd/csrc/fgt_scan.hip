@@ -644,9 +644,8 @@ hipError_t scan_out(const Workspace& w, const Modes& md, int64_t P, const T* b,
   const int kind = (out.val ? kOutVal : 0) | (out.der ? kOutDer : 0);
   switch (kind) {
     case kOutVal: return scan_nm<T, NM, kOutVal>(w, md, P, b, out, s, tl);
-    case kOutDer: return scan_nm<T, NM, kOutDer>(w, md, P, b, out, s, tl);
     case kOutVal | kOutDer: return scan_nm<T, NM, kOutVal | kOutDer>(w, md, P, b, out, s, tl);
-    default: return hipSuccess;   // nothing asked for
+    default: return hipErrorInvalidValue;   // the adjoint has its own kernels
   }
 }
 
@@ -660,43 +659,6 @@ __global__ __launch_bounds__(256) void k_gather(const uint32_t* __restrict__ ids
     const uint32_t o = ids[p] - lo;
     b[p] = o < n ? wts[o] : T(0);
   }
-}
-
-// Partial sums of sum_i (x_i - c) dx_i + sum_j (y_j - c) dy_j in double,
-// grid-stride (fixed order for a fixed grid), one partial per block.
-template <class T>
-__global__ __launch_bounds__(256) void k_delta_part(const void* keys0, const void* keys1,
-                                                    const PassInfo* __restrict__ pass, int64_t P,
-                                                    const T* __restrict__ x,
-                                                    const T* __restrict__ dx, int64_t M,
-                                                    const T* __restrict__ y,
-                                                    const T* __restrict__ dy, int64_t N,
-                                                    double* __restrict__ part) {
-  __shared__ double wsum[256 / kWave];
-  const void* keys = pass->final_buf ? keys1 : keys0;
-  const double c = 0.5 * ((double)key_value<T>(keys, 0) + (double)key_value<T>(keys, P - 1));
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double acc = 0.0;
-  for (int64_t i = t; i < M; i += stride) acc += ((double)x[i] - c) * (double)dx[i];
-  for (int64_t j = t; j < N; j += stride) acc += ((double)y[j] - c) * (double)dy[j];
-  for (int o = kWave / 2; o >= 1; o >>= 1) acc += shfl_xor(acc, o);
-  if (threadIdx.x % kWave == 0) wsum[threadIdx.x / kWave] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double sum = 0.0;
-    for (int w = 0; w < 256 / kWave; ++w) sum += wsum[w];
-    part[blockIdx.x] = sum;
-  }
-}
-
-template <class T>
-__global__ __launch_bounds__(kWave) void k_delta_final(const double* __restrict__ part, int nparts,
-                                                       double scale, T* __restrict__ out) {
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kWave) acc += part[i];
-  for (int o = kWave / 2; o >= 1; o >>= 1) acc += shfl_xor(acc, o);
-  if (threadIdx.x == 0) out[0] = (T)(scale * acc);
 }
 
 }  // namespace
@@ -727,16 +689,6 @@ hipError_t gather_strengths(const Workspace& w, int64_t P, uint32_t lo, uint32_t
 }
 
 template <class T>
-hipError_t delta_gradient(const Workspace& w, int64_t P, const T* x, const T* dx, int64_t M,
-                          const T* y, const T* dy, int64_t N, double delta, T* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_delta_part<T>, dim3(kRedBlocks), dim3(256), 0, s, w.keys[0], w.keys[1],
-                     w.pass, P, x, dx, M, y, dy, N, w.red);
-  hipLaunchKernelGGL(k_delta_final<T>, dim3(1), dim3(kWave), 0, s, (const double*)w.red,
-                     kRedBlocks, -0.5 / delta, out);
-  return hipGetLastError();
-}
-
-template <class T>
 hipError_t fill_zero(T* u, int64_t n, hipStream_t s) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
@@ -753,12 +705,6 @@ template hipError_t gather_strengths<double>(const Workspace&, int64_t, uint32_t
                                              const double*, double*, hipStream_t);
 template hipError_t gather_strengths<float>(const Workspace&, int64_t, uint32_t, uint32_t,
                                             const float*, float*, hipStream_t);
-template hipError_t delta_gradient<double>(const Workspace&, int64_t, const double*, const double*,
-                                           int64_t, const double*, const double*, int64_t, double,
-                                           double*, hipStream_t);
-template hipError_t delta_gradient<float>(const Workspace&, int64_t, const float*, const float*,
-                                          int64_t, const float*, const float*, int64_t, double,
-                                          float*, hipStream_t);
 template hipError_t fill_zero<double>(double*, int64_t, hipStream_t);
 template hipError_t fill_zero<float>(float*, int64_t, hipStream_t);
 

@@ -358,3 +358,23 @@ def test_grad_full_size_fp32_4digits():
     r2 = np.max(np.abs(dx[ti] - o_dx) / (np.abs(g32[ti]) * (2 * ep * sa + impl_tol_der(a32, p, P, EPS32))))
     r3 = np.max(np.abs(dy[sj] - o_dy) / (np.abs(a32[sj]) * (2 * ep * sg + impl_tol_der(g32, p, P, EPS32))))
     assert max(r1, r2, r3) <= 1.0
+
+
+def test_partial_requests_match_full():
+    """Any subset of outputs gives the same values as the full request."""
+    g0 = np.random.default_rng(16)
+    M, N = 6000, 5000
+    x, y = g0.random(M), g0.random(N)
+    a, g = g0.standard_normal(N), g0.standard_normal(M)
+    say("[gpu] fgt_backward partial requests")
+    p = fgt.plan(1e-4, 6)
+    X, Y, A, G = (to_dev(v, torch.float64) for v in (x, y, a, g))
+    ws = fgt.workspace(p, M, N, X.device)
+    fgt.eval(X, Y, A, p, ws=ws)
+    full = fgt.backward(X, Y, A, G, p, ws=ws, sorted=True)
+    only_dd = fgt.backward(X, Y, A, G, p, ws=ws, sorted=True, dalpha=False, dx=False, dy=False)
+    only_da = fgt.backward(X, Y, A, G, p, ws=ws, sorted=True, dx=False, dy=False, ddelta=False)
+    only_dx = fgt.backward(X, Y, A, G, p, ws=ws, sorted=True, dalpha=False, dy=False, ddelta=False)
+    assert only_dd[:3] == (None, None, None) and float(only_dd[3]) == float(full[3])
+    assert torch.equal(only_da[0], full[0]) and only_da[1] is None
+    assert torch.equal(only_dx[1], full[1]) and only_dx[2] is None

@@ -121,19 +121,17 @@ def test_backward_and_eval_sorted_validation():
     assert lib.fgt_plan(1e-3, 6, fgt.FGT_F64, ctypes.byref(h)) == fgt.FGT_OK
     d = ctypes.c_void_p(256)
     ws_ok = lib.fgt_workspace_size(h, 4, 4)
-    # ddelta needs dx and dy; unknown flags; null g; small workspace
-    assert lib.fgt_backward(h, d, 4, d, d, 4, d, d, None, d, d, 0, d, ws_ok, None) == fgt.FGT_EINVAL
-    assert lib.fgt_backward(h, d, 4, d, d, 4, d, d, d, None, d, 0, d, ws_ok, None) == fgt.FGT_EINVAL
+    # unknown flags; null g; small workspace; sorting needs x, y and alpha
     assert lib.fgt_backward(h, d, 4, d, d, 4, d, d, d, d, d, 2, d, ws_ok, None) == fgt.FGT_EINVAL
+    assert lib.fgt_backward(h, d, 4, d, None, 4, d, d, d, d, d, 0, d, ws_ok, None) == fgt.FGT_EINVAL
     assert lib.fgt_backward(h, d, 4, d, d, 4, None, d, d, d, d, 0, d, ws_ok, None) == fgt.FGT_EINVAL
     assert lib.fgt_backward(h, d, 4, d, d, 4, d, d, d, d, d, 0, d, ws_ok - 1, None) == fgt.FGT_EINVAL
     assert lib.fgt_backward(h, None, 4, d, d, 4, d, d, d, d, None, 0, d, ws_ok, None) == fgt.FGT_EINVAL
     assert lib.fgt_backward(None, d, 4, d, d, 4, d, d, d, d, d, 0, d, ws_ok, None) == fgt.FGT_EINVAL
+    assert lib.fgt_backward(h, None, 4, None, None, 4, d, d, d, d, d, fgt.FGT_SORTED,
+                            ctypes.c_void_p(257), ws_ok, None) == fgt.FGT_EINVAL
     # nothing requested: nothing to do
     assert lib.fgt_backward(h, d, 4, d, d, 4, d, None, None, None, None, 0, d, ws_ok, None) == fgt.FGT_OK
-    # with FGT_SORTED the coordinates are needed only for ddelta
-    assert lib.fgt_backward(h, None, 4, None, d, 4, d, d, d, d, d, fgt.FGT_SORTED, d, ws_ok,
-                            None) == fgt.FGT_EINVAL
     assert lib.fgt_eval_sorted(h, 4, 4, None, d, d, ws_ok, None) == fgt.FGT_EINVAL
     assert lib.fgt_eval_sorted(h, 4, 4, d, d, ctypes.c_void_p(257), ws_ok, None) == fgt.FGT_EINVAL
     assert lib.fgt_eval_sorted(h, 4, 4, d, d, d, ws_ok - 1, None) == fgt.FGT_EINVAL
