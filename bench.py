@@ -13,6 +13,10 @@ workspace: dL/dalpha, dL/dx, dL/dy and dL/ddelta for L = g . u, g ~ N(0,1)).
 [256, 65536], delta_b log-uniform in [1e-6, 1e-2], 16 columns, 6 digits),
 eagerly and as a replayed HIP graph, next to a loop of fgt_eval calls (one per
 transform and column) timed on 32 of the transforms and scaled to 4096.
+`plan_reuse` times fgt_eval_sorted (new strengths on the sorted points, the
+sort skipped).  `identical_points` times fgt_eval_self in the setting of the
+paper's Table 1 (targets = sources, N = 10^7 uniform on [0,1), delta = 1,
+n_e = 3..6), with Chebyshev points in order and the sort skipped beside it.
 `roofline` describes
 the kernel with the largest share of the step, timed with HIP events recorded
 by the library on its own stream during the timed steps; `cpu_baseline` is
@@ -50,6 +54,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the fwd+bwd timing")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched timing")
+    ap.add_argument("--no-identical", action="store_true",
+                    help="skip the identical-points (Table 1 setting) timing")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one plain device copy of this many bytes (counter calibration)")
     return ap.parse_args()
@@ -86,6 +92,41 @@ def cpu_baseline(x, y, a, delta, digits, n_modes, k):
         "sample": (f"first 2^{k} targets and 2^{k} sources of the same inputs, {digits} digits "
                    f"({n_modes} modes): O2 SOE recurrence in C (qsort, then one sweep per mode and "
                    f"direction, OpenMP over the {2 * n_modes} sweeps), {dt:.2f} s wall"),
+    }
+
+
+def bench_identical(args, fgt, W, torch, np, dev):
+    N = 10_000_000
+    x, a = W.identical_uniform(N)
+    X = torch.from_numpy(x).to(dev)
+    A = torch.from_numpy(a).to(dev)
+    Xc = torch.from_numpy(W.chebyshev(N)).to(dev)
+    U = torch.empty(N, dtype=torch.float64, device=dev)
+    rows = []
+    for digits in (5, 6, 8, 10):
+        p = fgt.plan(1.0, digits)
+        ws = fgt.workspace(p, 0, N, dev)
+        res = {"n_e": p.n_modes, "digits": digits}
+        for name, pts, pre in (("uniform", X, False), ("chebyshev_presorted", Xc, True)):
+            for _ in range(args.warmup):
+                fgt.eval_self(pts, A, p, presorted=pre, out=U, ws=ws)
+            torch.cuda.synchronize()
+            if fgt.last_device_status(ws) != fgt.FGT_OK:
+                raise RuntimeError("device status after identical-points warmup")
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fgt.eval_self(pts, A, p, presorted=pre, out=U, ws=ws)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            res[name] = {"ms": round(ms, 4), "points_per_s": N / (ms * 1e-3)}
+        rows.append(res)
+    return {
+        "workload": "targets = sources, N = 10^7 uniform on [0,1) (or Chebyshev in order), "
+                    "alpha ~ N(0,1), delta = 1, FP64",
+        "rows": rows,
+        "paper_context": ("Figure 7 (single core of an i7-4600U laptop): 2.6e6 to 1.7e6 points/s "
+                          "for n_e = 3..6 without precomputation, 1.6e7 to 9e6 points/s with the "
+                          "points pre-sorted and the exponentials precomputed"),
     }
 
 
@@ -315,6 +356,22 @@ def main():
             "ratio_to_fwd": round(ms_fb / ms_step, 4),
             "step": "fgt_eval + fgt_backward(FGT_SORTED) giving dL/dalpha, dL/dx, dL/dy, dL/ddelta",
         }
+    # plan reuse: new strengths on the sorted points
+    A2 = torch.from_numpy(np.random.default_rng(6).standard_normal(N)).to(dev, dtype)
+    fgt.eval(X, Y, A, p, out=u, ws=ws)
+    for _ in range(args.warmup):
+        fgt.eval_sorted(A2, p, ws, M, out=u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fgt.eval_sorted(A2, p, ws, M, out=u)
+    torch.cuda.synchronize()
+    ms_reuse = (time.perf_counter() - t0) * 1e3 / args.steps
+    out["plan_reuse"] = {"ms_per_step": round(ms_reuse, 5),
+                         "value": P * n_modes / (ms_reuse * 1e-3), "unit": "point-modes/s",
+                         "step": "fgt_eval_sorted: strengths gathered into the kept sort, then the scans"}
+    if not args.no_identical and not args.fp32:
+        out["identical_points"] = bench_identical(args, fgt, W, torch, np, dev)
     if not args.no_batched and not args.fp32:
         out["batched"] = bench_batched(args, fgt, W, torch, np, dev)
     if not args.no_cpu_baseline:

@@ -43,6 +43,7 @@ extern "C" {
 #define FGT_EUNSUPPORTED 2  /* valid request the library does not serve (e.g. FP32 beyond 6 digits) */
 #define FGT_ENONFINITE 3    /* a coordinate was NaN or infinite (reported by fgt_last_device_status) */
 #define FGT_EDEVICE 4       /* a HIP runtime call failed */
+#define FGT_EUNSORTED 5     /* FGT_PRESORTED given for points that are not in ascending order */
 
 /* Element types. */
 #define FGT_F64 0
@@ -116,6 +117,23 @@ int fgt_eval(fgt_plan_t plan, const void* x, int64_t M, const void* y, const voi
 
 /* Flag for fgt_backward: the workspace already holds the sort of (x, y). */
 #define FGT_SORTED 1
+/* Flag for fgt_eval_self: the points are already in ascending order. */
+#define FGT_PRESORTED 2
+
+/*
+ * fgt_eval_self -- the transform with targets identical to the sources
+ * (Section 5's first test case):  u_i = sum_j S(x_i - x_j) alpha_j,  i, j = 1..N,
+ * the self term included.  Every sorted point is then both a source and a
+ * target, so half as many points are sorted and scanned as with fgt_eval(x, x).
+ *   flags  0, or FGT_PRESORTED when x is already ascending (e.g. Chebyshev
+ *          points in order): the radix sort is skipped.  The order is checked on
+ *          the device; a violation is reported by fgt_last_device_status as
+ *          FGT_EUNSORTED (u is then unspecified).
+ *   ws     fgt_workspace_size(plan, 0, N) bytes, as for fgt_eval.
+ * N == 0 enqueues nothing.  Errors: as fgt_eval, plus FGT_EINVAL for unknown flags.
+ */
+int fgt_eval_self(fgt_plan_t plan, const void* x, int64_t N, const void* alpha, void* u, int flags,
+                  void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * fgt_eval_sorted -- fgt_eval for new strengths alpha[N] on points already
@@ -218,8 +236,8 @@ int fgt_eval_batched(int64_t B, const double* delta, int digits, int dtype, cons
 
 /*
  * fgt_last_device_status -- synchronise `stream`, then read and clear the
- * status word that the last fgt_eval on workspace `ws` left there.
- * Returns FGT_OK, FGT_ENONFINITE, or FGT_EINVAL / FGT_EDEVICE.
+ * status word that the last call on workspace `ws` left there.
+ * Returns FGT_OK, FGT_ENONFINITE, FGT_EUNSORTED, or FGT_EINVAL / FGT_EDEVICE.
  */
 int fgt_last_device_status(void* ws, hipStream_t stream);
 

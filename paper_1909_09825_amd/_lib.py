@@ -11,10 +11,11 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libfgt.so")
 
-FGT_OK, FGT_EINVAL, FGT_EUNSUPPORTED, FGT_ENONFINITE, FGT_EDEVICE = 0, 1, 2, 3, 4
+FGT_OK, FGT_EINVAL, FGT_EUNSUPPORTED, FGT_ENONFINITE, FGT_EDEVICE, FGT_EUNSORTED = 0, 1, 2, 3, 4, 5
 FGT_F64, FGT_F32 = 0, 1
 FGT_MAX_MODES = 8
 FGT_SORTED = 1
+FGT_PRESORTED = 2
 
 _lib = None
 
@@ -48,6 +49,8 @@ def load() -> ctypes.CDLL:
     lib.fgt_eval.restype = c_int
     lib.fgt_eval_sorted.argtypes = [vp, c_i64, c_i64, vp, vp, vp, ctypes.c_size_t, vp]
     lib.fgt_eval_sorted.restype = c_int
+    lib.fgt_eval_self.argtypes = [vp, vp, c_i64, vp, vp, c_int, vp, ctypes.c_size_t, vp]
+    lib.fgt_eval_self.restype = c_int
     lib.fgt_backward.argtypes = [vp, vp, c_i64, vp, vp, c_i64, vp, vp, vp, vp, vp, c_int, vp,
                                  ctypes.c_size_t, vp]
     lib.fgt_backward.restype = c_int

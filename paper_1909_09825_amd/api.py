@@ -133,6 +133,37 @@ def _check_ws(p: Plan, ws: torch.Tensor, M: int, N: int, dev) -> int:
     return need
 
 
+def eval_self(x: torch.Tensor, alpha: torch.Tensor, p: Plan, presorted: bool = False,
+              out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """u_i = sum_j S(x_i - x_j) alpha_j: targets identical to the sources.
+
+    presorted=True skips the sort for points already in ascending order (the
+    order is checked on the device; see last_device_status).
+    """
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise ValueError("x must be a CUDA (HIP) tensor")
+    dev = x.device
+    x = _vec(x, "x", p.dtype, dev)
+    alpha = _vec(alpha, "alpha", p.dtype, dev)
+    N = x.shape[0]
+    if alpha.shape[0] != N:
+        raise ValueError("x and alpha must have the same length")
+    if out is None:
+        out = torch.empty(N, dtype=p.dtype, device=dev)
+    else:
+        out = _vec(out, "out", p.dtype, dev)
+        if out.shape[0] != N:
+            raise ValueError("out must have length N")
+    if ws is None:
+        ws = workspace(p, 0, N, dev)
+    need = _check_ws(p, ws, 0, N, dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = p._lib.fgt_eval_self(p.handle, x.data_ptr(), N, alpha.data_ptr(), out.data_ptr(),
+                              _lib.FGT_PRESORTED if presorted else 0, ws.data_ptr(), need, stream)
+    check(rc, "fgt_eval_self")
+    return out
+
+
 def eval_sorted(alpha: torch.Tensor, p: Plan, ws: torch.Tensor, M: int,
                 out: torch.Tensor | None = None) -> torch.Tensor:
     """u for new strengths on the points whose sort `ws` holds (from eval or backward).

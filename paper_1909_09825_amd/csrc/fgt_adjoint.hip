@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kScanThreads) void k_adj_final_fast(
 #pragma unroll
     for (int d = kTaylorMax; d >= 1; --d)
       if (rr <= md.taylor_thr[d]) D = d;
-    const T dz_lim = T(md.taylor_thr[kTaylorMax] / md.tau_abs[k]);
+    const T dz_lim = T(md.dz_lim[k]);
     C<T> ex[kScanChunk];
 #pragma unroll
     for (int j = 0; j < kScanChunk; ++j) ex[j] = {T(0), T(0)};
@@ -557,7 +557,7 @@ __global__ __launch_bounds__(kScanThreads) void k_adj_final(
 #pragma unroll
     for (int d = kTaylorMax; d >= 1; --d)
       if (rr <= md.taylor_thr[d]) D = d;
-    const T dz_lim = T(md.taylor_thr[kTaylorMax] / md.tau_abs[k]);
+    const T dz_lim = T(md.dz_lim[k]);
     C<T> ex[kScanChunk];
 #pragma unroll
     for (int j = 0; j < kScanChunk; ++j) ex[j] = {T(0), T(0)};

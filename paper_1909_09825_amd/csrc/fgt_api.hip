@@ -154,6 +154,7 @@ void make_modes(const SoeTable* tab, double delta, int dtype, Modes* m) {
     fact *= (d + 1);   // (d+1)!
     m->taylor_thr[d] = pow(unit * fact, 1.0 / (d + 1));
   }
+  for (int k = 0; k < tab->n_modes; ++k) m->dz_lim[k] = m->taylor_thr[kTaylorMax] / m->tau_abs[k];
 }
 
 // Benchmark timing state (see fgt_profile_begin).
@@ -228,6 +229,7 @@ const char* fgt_strerror(int status) {
     case FGT_EUNSUPPORTED: return "unsupported request";
     case FGT_ENONFINITE: return "non-finite coordinate";
     case FGT_EDEVICE: return "HIP runtime error";
+    case FGT_EUNSORTED: return "points not in ascending order";
     default: return "unknown status";
   }
 }
@@ -338,6 +340,44 @@ int fgt_eval_sorted(fgt_plan_t plan, int64_t M, int64_t N, const void* alpha, vo
   fgt::Timeline none;
   hipError_t e = f64 ? fgt::forward<double>(plan, w, nullptr, M, nullptr, alpha, N, u, false, stream, &none)
                      : fgt::forward<float>(plan, w, nullptr, M, nullptr, alpha, N, u, false, stream, &none);
+  return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+}
+
+int fgt_eval_self(fgt_plan_t plan, const void* x, int64_t N, const void* alpha, void* u, int flags,
+                  void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!plan || N < 0) return FGT_EINVAL;
+  if (N >= (int64_t(1) << 32)) return FGT_EINVAL;
+  if (flags & ~FGT_PRESORTED) return FGT_EINVAL;
+  if (N == 0) return FGT_OK;
+  if (!x || !alpha || !u || !ws) return FGT_EINVAL;
+  if (((uintptr_t)ws & 255u) != 0) return FGT_EINVAL;
+  const bool f64 = plan->dtype == FGT_F64;
+  const fgt::Workspace w = fgt::layout(ws, N, f64 ? 8 : 4, plan->modes.n);
+  if (ws_bytes < w.total) return FGT_EINVAL;
+  fgt::Timeline none;
+  hipError_t e;
+  // Every point is a source (strength alpha) and a target (output u): merged ids in [0, N).
+  if (f64) {
+    e = (flags & FGT_PRESORTED)
+            ? fgt::presorted_points<double>(w, (const double*)x, (const double*)alpha, N, stream)
+            : fgt::sort_points<double>(w, nullptr, 0, (const double*)x, (const double*)alpha, N,
+                                       plan->modes.key_width, stream, &none);
+    if (e == hipSuccess)
+      e = fgt::scan_points<double>(w, plan->modes, N,
+                                   (flags & FGT_PRESORTED) ? (const double*)alpha : (const double*)w.b,
+                                   fgt::ScanOut<double>{(double*)u, nullptr, nullptr, 0u, (uint32_t)N},
+                                   stream, &none);
+  } else {
+    e = (flags & FGT_PRESORTED)
+            ? fgt::presorted_points<float>(w, (const float*)x, (const float*)alpha, N, stream)
+            : fgt::sort_points<float>(w, nullptr, 0, (const float*)x, (const float*)alpha, N,
+                                      plan->modes.key_width, stream, &none);
+    if (e == hipSuccess)
+      e = fgt::scan_points<float>(w, plan->modes, N,
+                                   (flags & FGT_PRESORTED) ? (const float*)alpha : (const float*)w.b,
+                                  fgt::ScanOut<float>{(float*)u, nullptr, nullptr, 0u, (uint32_t)N},
+                                  stream, &none);
+  }
   return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
 }
 
@@ -634,6 +674,7 @@ int fgt_last_device_status(void* ws, hipStream_t stream) {
   if (hipMemcpy(status, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
     return FGT_EDEVICE;
   if (v & fgt::kStatusNonFinite) return FGT_ENONFINITE;
+  if (v & fgt::kStatusUnsorted) return FGT_EUNSORTED;
   return v ? FGT_EDEVICE : FGT_OK;
 }
 

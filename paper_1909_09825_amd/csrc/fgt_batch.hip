@@ -619,7 +619,7 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
 #pragma unroll
       for (int d = kTaylorMax; d >= 1; --d)
         if (rr <= md.taylor_thr[d]) D = d;
-      const double dz_lim = md.taylor_thr[kTaylorMax] / md.tau_abs[k];
+      const double dz_lim = md.dz_lim[k];
       // A gap beyond the Taylor range is halved k times into it, its
       // exponential taken there and squared k times
       // (exp(-tau dz) = exp(-tau dz / 2^k)^(2^k)): the relative error grows to

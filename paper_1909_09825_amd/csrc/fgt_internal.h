@@ -35,6 +35,9 @@ struct Modes {
   double tau_abs_max;
   double taylor_thr[kTaylorMax + 1];
   double key_width;   // sort resolution in coordinate units (see fgt_plan)
+  // Largest gap whose exponential the degree-kTaylorMax polynomial serves:
+  // taylor_thr[kTaylorMax] / |tau_k|.
+  double dz_lim[FGT_MAX_MODES];
   // Taylor coefficients of exp(-tau_k x) in x: (-tau_k)^m / m!.
   double coef_re[FGT_MAX_MODES][kTaylorMax + 1];
   double coef_im[FGT_MAX_MODES][kTaylorMax + 1];
@@ -116,6 +119,7 @@ constexpr uint32_t kNoSlot = 0xffffffffu;
 // Bits of the device status word.
 constexpr uint32_t kStatusNonFinite = 1u;
 constexpr uint32_t kStatusInternal = 2u;
+constexpr uint32_t kStatusUnsorted = 4u;
 
 // ---------------------------------------------------------------------------
 // Workspace layout (all offsets 256-byte aligned).
@@ -198,6 +202,12 @@ hipError_t adjoint_points(const Workspace& w, const Modes& md, int64_t M, int64_
                           T* dx, T* dalpha, T* dy, T* ddelta, double delta, hipStream_t s);
 template <class T>
 hipError_t fill_zero(T* u, int64_t n, hipStream_t s);
+// Points given in ascending order: keys and identity ids written as the sort
+// would leave them (the scan then reads alpha in place); order and finiteness
+// checked.
+template <class T>
+hipError_t presorted_points(const Workspace& w, const T* x, const T* alpha, int64_t N,
+                            hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Batched transforms (B independent transforms in CSR layout, R strength

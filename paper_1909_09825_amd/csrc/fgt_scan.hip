@@ -303,7 +303,7 @@ __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const
 #pragma unroll
     for (int d = kTaylorMax; d >= 1; --d)
       if (rr <= md.taylor_thr[d]) D = d;
-    const T dz_lim = T(md.taylor_thr[kTaylorMax] / md.tau_abs[k]);
+    const T dz_lim = T(md.dz_lim[k]);
 
     // e_j = sum_{m<=D} (-tau)^m dz_j^m / m!  (Horner in the real variable dz)
     C<T> ex[kScanChunk];
@@ -569,7 +569,7 @@ __global__ __launch_bounds__(kScanThreads) void k_final_fast(
 #pragma unroll
     for (int d = kTaylorMax; d >= 1; --d)
       if (rr <= md.taylor_thr[d]) D = d;
-    const T dz_lim = T(md.taylor_thr[kTaylorMax] / md.tau_abs[k]);
+    const T dz_lim = T(md.dz_lim[k]);
     C<T> ex[kScanChunk];
 #pragma unroll
     for (int j = 0; j < kScanChunk; ++j) ex[j] = {T(0), T(0)};

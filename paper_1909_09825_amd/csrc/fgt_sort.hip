@@ -425,7 +425,50 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   }
 }
 
+// Points given in ascending order: keys and identity ids as the sort would
+// leave them (the strengths are read in place).
+template <class T>
+__global__ __launch_bounds__(256) void k_presorted(const T* __restrict__ x, int64_t N,
+                                                   void* keys0, uint32_t* __restrict__ ids,
+                                                   PassInfo* __restrict__ pass,
+                                                   uint32_t* __restrict__ status) {
+  using K = typename KeyOf<T>::type;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool unsorted = false, bad = false;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
+    const T z = x[p];
+    bad |= !isfinite(z);
+    if (p > 0) unsorted |= z < x[p - 1];
+    ((K*)keys0)[p] = to_key(z);
+    ids[p] = (uint32_t)p;
+  }
+  if (unsorted) atomicOr(status, kStatusUnsorted);
+  if (bad) atomicOr(status, kStatusNonFinite);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    pass->final_buf = 0;
+    pass->last_pass = -1;
+  }
+}
+
 }  // namespace
+
+template <class T>
+hipError_t presorted_points(const Workspace& w, const T* x, const T* alpha, int64_t N,
+                            hipStream_t s) {
+  (void)alpha;
+  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, w.status, (size_t)64);
+  int64_t blocks = (N + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_presorted<T>, dim3((unsigned)blocks), dim3(256), 0, s, x, N, w.keys[0],
+                     w.ids, w.pass, w.status);
+  return hipGetLastError();
+}
+
+template hipError_t presorted_points<double>(const Workspace&, const double*, const double*,
+                                             int64_t, hipStream_t);
+template hipError_t presorted_points<float>(const Workspace&, const float*, const float*, int64_t,
+                                            hipStream_t);
 
 template <class T>
 hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, const T* alpha,

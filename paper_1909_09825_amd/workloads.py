@@ -139,6 +139,20 @@ def grad_problem(log2n: int = 22, delta: float = 1e-4, digits: int = 9, sub: int
     return Problem(x, y, a, float(delta), int(digits), f"grad_N{n}_d{delta:g}_D{digits}"), w
 
 
+def identical_uniform(N: int = 10_000_000, delta: float = 1.0, digits: int = 6, sub: int = 0):
+    """Targets identical to N sources uniform on [0,1), alpha ~ N(0,1) (Table 1 setting)."""
+    g = rng(6, sub)
+    x = g.random(N)
+    a = g.standard_normal(N)
+    return x, a
+
+
+def chebyshev(N: int) -> np.ndarray:
+    """Chebyshev points of the first kind mapped to [0,1], in ascending order."""
+    i = np.arange(1, N + 1, dtype=np.float64)
+    return 0.5 * (1.0 - np.cos(np.pi * (i - 0.5) / N))
+
+
 def sample_indices(M: int, k: int, cfg: int, sub: int = 1) -> np.ndarray:
     """k distinct target indices drawn without replacement (sorted)."""
     g = rng(cfg, 100 + sub)
