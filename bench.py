@@ -139,6 +139,9 @@ def bench_batched(args, fgt, W, torch, np, dev):
     A = torch.from_numpy(bt.alpha).to(dev)
     U = torch.empty((bp.M, R), dtype=torch.float64, device=dev)
     ws = fgt.batch_workspace(bp, dev)
+    t0 = time.perf_counter()
+    config = bp.tune(X, Y, A, ws=ws)
+    tune_s = time.perf_counter() - t0
     for _ in range(args.warmup):
         fgt.eval_batch(X, Y, A, bp, out=U, ws=ws)
     torch.cuda.synchronize()
@@ -202,6 +205,8 @@ def bench_batched(args, fgt, W, torch, np, dev):
         "loop_sample": (f"fgt_eval once per column on 32 sampled transforms ({pts32} points), "
                         f"{ms_loop32:.1f} ms, scaled by total points"),
         "speedup_vs_loop": round(ms_loop / ms, 1),
+        "tuned_config": {"points_per_lane": config[0], "bucket_points": config[1],
+                         "tuning_s": round(tune_s, 2)},
     }
 
 

@@ -219,6 +219,25 @@ int fgt_batch_info(fgt_batch_t plan, int* n_modes, double* err_bound, int64_t* t
 int fgt_batch_eval(fgt_batch_t plan, const void* x, const void* y, const void* alpha, void* u,
                    void* ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Autotuning.  Two choices shape the batched kernels: the points each lane
+ * runs per column in the scan (`chunk`: 8 or 16) and the size the sort aims
+ * for when it splits a transform into LDS-sorted buckets (`bucket_points`:
+ * 1024 or 2048).  fgt_batch_tune times the four combinations on the given
+ * data (one warm-up and three timed fgt_batch_eval calls each, HIP events on
+ * `stream`, which it synchronises), keeps the fastest in the plan and, if
+ * `cache_path` is not null, records it in that JSON file under a key made of
+ * the architecture, log2 of B and of the total points, R and the mode count;
+ * a later call with a matching key takes the recorded choice without timing.
+ * u and ws are overwritten.  fgt_batch_config / fgt_batch_set_config read and
+ * set the choice directly (default: chunk 16, buckets of 2048).
+ * Errors: FGT_EINVAL (null plan, values outside the choices), as fgt_batch_eval.
+ */
+int fgt_batch_tune(fgt_batch_t plan, const void* x, const void* y, const void* alpha, void* u,
+                   void* ws, size_t ws_bytes, hipStream_t stream, const char* cache_path);
+int fgt_batch_config(fgt_batch_t plan, int* chunk, int* bucket_points);
+int fgt_batch_set_config(fgt_batch_t plan, int chunk, int bucket_points);
+
 /* Release a batch plan.  Accepts null. */
 void fgt_batch_destroy(fgt_batch_t plan);
 

@@ -63,6 +63,12 @@ def load() -> ctypes.CDLL:
     lib.fgt_batch_info.restype = c_int
     lib.fgt_batch_eval.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.fgt_batch_eval.restype = c_int
+    lib.fgt_batch_tune.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.c_char_p]
+    lib.fgt_batch_tune.restype = c_int
+    lib.fgt_batch_config.argtypes = [vp, ip, ip]
+    lib.fgt_batch_config.restype = c_int
+    lib.fgt_batch_set_config.argtypes = [vp, c_int, c_int]
+    lib.fgt_batch_set_config.restype = c_int
     lib.fgt_batch_destroy.argtypes = [vp]
     lib.fgt_batch_destroy.restype = None
     lib.fgt_eval_batched_workspace_size.argtypes = [c_i64, i64p, i64p, c_int, c_int]

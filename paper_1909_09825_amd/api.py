@@ -308,6 +308,34 @@ class BatchPlan:
     def workspace_size(self) -> int:
         return int(self._lib.fgt_batch_workspace_size(self._h))
 
+    @property
+    def config(self) -> tuple[int, int]:
+        """(points per lane in the scan, target bucket size of the sort)."""
+        c, b = ctypes.c_int(), ctypes.c_int()
+        check(self._lib.fgt_batch_config(self._h, ctypes.byref(c), ctypes.byref(b)), "fgt_batch_config")
+        return c.value, b.value
+
+    def set_config(self, chunk: int, bucket_points: int) -> None:
+        check(self._lib.fgt_batch_set_config(self._h, int(chunk), int(bucket_points)),
+              "fgt_batch_set_config")
+
+    def tune(self, x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor,
+             ws: torch.Tensor | None = None, cache: str | None = None) -> tuple[int, int]:
+        """Time the kernel choices on this data (or take them from the JSON cache); returns config."""
+        u = torch.empty((self.M, self.R), dtype=self.dtype, device=x.device)
+        if alpha.dim() == 1:
+            alpha = alpha.reshape(-1, 1)
+        alpha = alpha.contiguous()
+        if ws is None:
+            ws = batch_workspace(self, x.device)
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+        rc = self._lib.fgt_batch_tune(self._h, x.contiguous().data_ptr(), y.contiguous().data_ptr(),
+                                      alpha.data_ptr(), u.data_ptr(), ws.data_ptr(),
+                                      self.workspace_size(), stream,
+                                      cache.encode() if cache else None)
+        check(rc, "fgt_batch_tune")
+        return self.config
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:

@@ -3,7 +3,11 @@
 #include <math.h>
 #include <string.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <new>
+#include <string>
 #include <vector>
 
 #include "fgt_internal.h"
@@ -420,31 +424,41 @@ struct fgt_batch_s {
   int digits;
   fgt::Modes modes;        // the table at delta = 1
   double s_allow;          // sort resolution in scaled coordinates
-  fgt::BatchDims dims;
-  int max_nb_log2;
-  fgt::SegInfo* d_seg;
+  fgt::BatchDims dims;     // sizes for the workspace: maxima over the tunable choices
+  // Device tables for the two bucket sizes the autotuner chooses between.
+  fgt::SegInfo* d_seg[2];
+  fgt::BucketInfo* d_buckets[2];
+  int64_t n_buckets[2];
+  int max_nb_log2[2];
   fgt::ChunkInfo* d_chunks;
-  fgt::BucketInfo* d_buckets;
   int64_t* d_ne_base;
   double* d_ne_scale;
+  int chunk;               // points per lane in the scan: 8 or 16
+  int bucket_sel;          // 0: buckets of about 2048 points, 1: about 1024
 };
 
 namespace fgt {
 namespace {
 
+constexpr int kBucketTargets[2] = {2048, 1024};
+constexpr int kChunkChoices[2] = {16, 8};
+
 void batch_free(fgt_batch_s* b) {
   if (!b) return;
-  if (b->d_seg) (void)hipFree(b->d_seg);
+  for (int i = 0; i < 2; ++i) {
+    if (b->d_seg[i]) (void)hipFree(b->d_seg[i]);
+    if (b->d_buckets[i]) (void)hipFree(b->d_buckets[i]);
+  }
   if (b->d_chunks) (void)hipFree(b->d_chunks);
-  if (b->d_buckets) (void)hipFree(b->d_buckets);
   if (b->d_ne_base) (void)hipFree(b->d_ne_base);
   if (b->d_ne_scale) (void)hipFree(b->d_ne_scale);
   delete b;
 }
 
-// Host part of a batch plan: validation, per-transform tables, sizes.
+// Host part of a batch plan for one bucket size: validation, per-transform
+// tables, sizes.
 int batch_tables(int64_t B, const double* delta, const int64_t* x_off, const int64_t* y_off, int R,
-                 std::vector<SegInfo>& seg, std::vector<ChunkInfo>& chunks,
+                 int bucket_target, std::vector<SegInfo>& seg, std::vector<ChunkInfo>& chunks,
                  std::vector<BucketInfo>& buckets, std::vector<int64_t>& ne_base,
                  std::vector<double>& ne_scale, BatchDims& d, int& max_nb_log2) {
   if (B < 0 || R < 1 || R > 64) return FGT_EINVAL;
@@ -452,6 +466,11 @@ int batch_tables(int64_t B, const double* delta, const int64_t* x_off, const int
   if (B > (int64_t(1) << 30)) return FGT_EINVAL;
   if (B > 0 && (x_off[0] != 0 || y_off[0] != 0)) return FGT_EINVAL;
   memset(&d, 0, sizeof(d));
+  seg.clear();
+  chunks.clear();
+  buckets.clear();
+  ne_base.clear();
+  ne_scale.clear();
   d.B = B;
   d.R = R;
   max_nb_log2 = 0;
@@ -473,7 +492,7 @@ int batch_tables(int64_t B, const double* delta, const int64_t* x_off, const int
     if (!isfinite(sg.scale)) return FGT_EINVAL;
     sg.n_chunks = (int32_t)((Pb + kBChunk - 1) / kBChunk);
     int lg = 0;
-    while (lg < kMaxBucketLog2 && ((int64_t)kBucketTarget << lg) < Pb) ++lg;
+    while (lg < kMaxBucketLog2 && ((int64_t)bucket_target << lg) < Pb) ++lg;
     sg.nb_log2 = lg;
     if (lg > max_nb_log2) max_nb_log2 = lg;
     sg.chunk0 = chunk0;
@@ -498,8 +517,30 @@ int batch_tables(int64_t B, const double* delta, const int64_t* x_off, const int
   d.n_buckets = bucket0;
   d.n_counts = cnt0;
   d.K = (int64_t)ne_base.size();
-  d.tiles = (d.P + kBTile - 1) / kBTile;
+  d.tiles = (d.P + kBTileMin - 1) / kBTileMin;   // the most tiles any chunk choice uses
   if (d.tiles < 1) d.tiles = 1;
+  return FGT_OK;
+}
+
+// Workspace sizes covering both bucket sizes.
+int batch_dims(int64_t B, const double* delta, const int64_t* x_off, const int64_t* y_off, int R,
+               int n_modes, BatchDims& d) {
+  std::vector<SegInfo> seg;
+  std::vector<ChunkInfo> chunks;
+  std::vector<BucketInfo> buckets;
+  std::vector<int64_t> ne_base;
+  std::vector<double> ne_scale;
+  BatchDims d1;
+  int lg = 0;
+  int rc = batch_tables(B, delta, x_off, y_off, R, kBucketTargets[0], seg, chunks, buckets, ne_base,
+                        ne_scale, d, lg);
+  if (rc != FGT_OK) return rc;
+  rc = batch_tables(B, delta, x_off, y_off, R, kBucketTargets[1], seg, chunks, buckets, ne_base,
+                    ne_scale, d1, lg);
+  if (rc != FGT_OK) return rc;
+  if (d1.n_buckets > d.n_buckets) d.n_buckets = d1.n_buckets;
+  if (d1.n_counts > d.n_counts) d.n_counts = d1.n_counts;
+  d.n_modes = n_modes;
   return FGT_OK;
 }
 
@@ -511,6 +552,79 @@ hipError_t upload(const std::vector<V>& v, V** out) {
   if (e != hipSuccess) return e;
   if (!v.empty()) e = hipMemcpy(*out, v.data(), sizeof(V) * v.size(), hipMemcpyHostToDevice);
   return e;
+}
+
+BatchTables tables_of(const fgt_batch_s* b) {
+  const int i = b->bucket_sel;
+  return BatchTables{b->d_seg[i], b->d_chunks, b->d_buckets[i], b->d_ne_base, b->d_ne_scale,
+                     b->n_buckets[i], b->max_nb_log2[i]};
+}
+
+// Shape signature of a batch for the tuning cache.
+void batch_signature(const fgt_batch_s* b, char* out, size_t n) {
+  int lgP = 0;
+  while (lgP < 62 && (int64_t(1) << lgP) < b->dims.P) ++lgP;
+  int lgB = 0;
+  while (lgB < 62 && (int64_t(1) << lgB) < b->dims.B) ++lgB;
+  snprintf(out, n, "gfx950:B2^%d:P2^%d:R%d:modes%d", lgB, lgP, b->dims.R, b->modes.n);
+}
+
+// Reads "<sig>": {"chunk": c, "bucket": k ...} from a cache file written by
+// fgt_batch_tune.  Returns true if found.
+bool cache_lookup(const char* path, const char* sig, int* chunk, int* bucket) {
+  FILE* f = fopen(path, "rb");
+  if (!f) return false;
+  std::vector<char> buf;
+  char tmp[4096];
+  size_t got;
+  while ((got = fread(tmp, 1, sizeof(tmp), f)) > 0) buf.insert(buf.end(), tmp, tmp + got);
+  fclose(f);
+  buf.push_back('\0');
+  std::string key = std::string("\"") + sig + "\"";
+  const char* at = strstr(buf.data(), key.c_str());
+  if (!at) return false;
+  const char* c = strstr(at, "\"chunk\":");
+  const char* k = strstr(at, "\"bucket\":");
+  const char* end = strchr(at, '}');
+  if (!c || !k || !end || c > end || k > end) return false;
+  const int cv = atoi(c + 8), kv = atoi(k + 9);
+  if ((cv != 8 && cv != 16) || (kv != 1024 && kv != 2048)) return false;
+  *chunk = cv;
+  *bucket = kv;
+  return true;
+}
+
+// Rewrites the cache file with this signature's entry replaced or added.
+void cache_store(const char* path, const char* sig, int chunk, int bucket, const double* ms,
+                 int n_candidates) {
+  std::vector<std::string> lines;
+  if (FILE* f = fopen(path, "rb")) {
+    char line[4096];
+    while (fgets(line, sizeof(line), f)) {
+      std::string l(line);
+      if (l.find("\"gfx950:") != std::string::npos && l.find(std::string("\"") + sig + "\"") == std::string::npos)
+        lines.push_back(l.substr(0, l.find_last_not_of(",\n\r ") + 1));
+    }
+    fclose(f);
+  }
+  char entry[1024];
+  int off = snprintf(entry, sizeof(entry), "  \"%s\": {\"chunk\": %d, \"bucket\": %d, \"ms\": [", sig,
+                     chunk, bucket);
+  for (int i = 0; i < n_candidates && off < (int)sizeof(entry) - 32; ++i)
+    off += snprintf(entry + off, sizeof(entry) - off, "%s%.4f", i ? ", " : "", ms[i]);
+  snprintf(entry + off, sizeof(entry) - off, "]}");
+  lines.push_back(entry);
+  std::string tmp_path = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp_path.c_str(), "wb");
+  if (!f) return;
+  fputs("{\n", f);
+  for (size_t i = 0; i < lines.size(); ++i) {
+    fputs(lines[i].c_str(), f);
+    fputs(i + 1 < lines.size() ? ",\n" : "\n", f);
+  }
+  fputs("}\n", f);
+  fclose(f);
+  (void)rename(tmp_path.c_str(), path);
 }
 
 }  // namespace
@@ -527,15 +641,8 @@ int fgt_batch_plan(int64_t B, const double* delta, int digits, int dtype, const 
   if (dtype != FGT_F64) return FGT_EUNSUPPORTED;
   const fgt::SoeTable* tab = fgt::choose_table(digits);
   if (!tab) return FGT_EUNSUPPORTED;
-  std::vector<fgt::SegInfo> seg;
-  std::vector<fgt::ChunkInfo> chunks;
-  std::vector<fgt::BucketInfo> buckets;
-  std::vector<int64_t> ne_base;
-  std::vector<double> ne_scale;
   fgt::BatchDims d;
-  int max_lg = 0;
-  int rc = fgt::batch_tables(B, delta, x_off, y_off, R, seg, chunks, buckets, ne_base, ne_scale, d,
-                             max_lg);
+  int rc = fgt::batch_dims(B, delta, x_off, y_off, R, tab->n_modes, d);
   if (rc != FGT_OK) return rc;
   fgt_batch_s* b = new (std::nothrow) fgt_batch_s;
   if (!b) return FGT_EINVAL;
@@ -543,15 +650,31 @@ int fgt_batch_plan(int64_t B, const double* delta, int digits, int dtype, const 
   b->digits = digits;
   fgt::make_modes(tab, 1.0, FGT_F64, &b->modes);
   b->s_allow = b->modes.key_width;
-  d.n_modes = b->modes.n;
   b->dims = d;
-  b->max_nb_log2 = max_lg;
-  if (fgt::upload(seg, &b->d_seg) != hipSuccess || fgt::upload(chunks, &b->d_chunks) != hipSuccess ||
-      fgt::upload(buckets, &b->d_buckets) != hipSuccess ||
-      fgt::upload(ne_base, &b->d_ne_base) != hipSuccess ||
-      fgt::upload(ne_scale, &b->d_ne_scale) != hipSuccess) {
-    fgt::batch_free(b);
-    return FGT_EDEVICE;
+  b->chunk = fgt::kChunkChoices[0];
+  b->bucket_sel = 0;
+  for (int i = 0; i < 2; ++i) {
+    std::vector<fgt::SegInfo> seg;
+    std::vector<fgt::ChunkInfo> chunks;
+    std::vector<fgt::BucketInfo> buckets;
+    std::vector<int64_t> ne_base;
+    std::vector<double> ne_scale;
+    fgt::BatchDims di;
+    int lg = 0;
+    (void)fgt::batch_tables(B, delta, x_off, y_off, R, fgt::kBucketTargets[i], seg, chunks, buckets,
+                            ne_base, ne_scale, di, lg);
+    b->n_buckets[i] = di.n_buckets;
+    b->max_nb_log2[i] = lg;
+    bool ok = fgt::upload(seg, &b->d_seg[i]) == hipSuccess &&
+              fgt::upload(buckets, &b->d_buckets[i]) == hipSuccess;
+    if (ok && i == 0)
+      ok = fgt::upload(chunks, &b->d_chunks) == hipSuccess &&
+           fgt::upload(ne_base, &b->d_ne_base) == hipSuccess &&
+           fgt::upload(ne_scale, &b->d_ne_scale) == hipSuccess;
+    if (!ok) {
+      fgt::batch_free(b);
+      return FGT_EDEVICE;
+    }
   }
   *out = b;
   return FGT_OK;
@@ -570,6 +693,23 @@ int fgt_batch_info(fgt_batch_t plan, int* n_modes, double* err_bound, int64_t* t
   return FGT_OK;
 }
 
+int fgt_batch_config(fgt_batch_t plan, int* chunk, int* bucket_points) {
+  if (!plan) return FGT_EINVAL;
+  if (chunk) *chunk = plan->chunk;
+  if (bucket_points) *bucket_points = fgt::kBucketTargets[plan->bucket_sel];
+  return FGT_OK;
+}
+
+int fgt_batch_set_config(fgt_batch_t plan, int chunk, int bucket_points) {
+  if (!plan) return FGT_EINVAL;
+  if (chunk != 8 && chunk != 16) return FGT_EINVAL;
+  if (bucket_points != fgt::kBucketTargets[0] && bucket_points != fgt::kBucketTargets[1])
+    return FGT_EINVAL;
+  plan->chunk = chunk;
+  plan->bucket_sel = bucket_points == fgt::kBucketTargets[0] ? 0 : 1;
+  return FGT_OK;
+}
+
 int fgt_batch_eval(fgt_batch_t plan, const void* x, const void* y, const void* alpha, void* u,
                    void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!plan) return FGT_EINVAL;
@@ -578,12 +718,52 @@ int fgt_batch_eval(fgt_batch_t plan, const void* x, const void* y, const void* a
   if (((uintptr_t)ws & 255u) != 0) return FGT_EINVAL;
   const fgt::BatchWork w = fgt::batch_layout(ws, d);
   if (ws_bytes < w.total) return FGT_EINVAL;
-  hipError_t e = fgt::batch_eval_launch(d, plan->modes, plan->s_allow, plan->d_seg,
-                                        plan->d_chunks, plan->d_buckets, plan->d_ne_base,
-                                        plan->d_ne_scale, plan->max_nb_log2,
-                                        (const double*)x, (const double*)y, (const double*)alpha,
-                                        (double*)u, w, stream);
+  hipError_t e = fgt::batch_eval_launch(d, fgt::tables_of(plan), plan->modes, plan->s_allow,
+                                        plan->chunk, (const double*)x, (const double*)y,
+                                        (const double*)alpha, (double*)u, w, stream);
   return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+}
+
+int fgt_batch_tune(fgt_batch_t plan, const void* x, const void* y, const void* alpha, void* u,
+                   void* ws, size_t ws_bytes, hipStream_t stream, const char* cache_path) {
+  if (!plan) return FGT_EINVAL;
+  char sig[160];
+  fgt::batch_signature(plan, sig, sizeof(sig));
+  int chunk = 0, bucket = 0;
+  if (cache_path && fgt::cache_lookup(cache_path, sig, &chunk, &bucket))
+    return fgt_batch_set_config(plan, chunk, bucket);
+  hipEvent_t ev[2];
+  if (hipEventCreate(&ev[0]) != hipSuccess) return FGT_EDEVICE;
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return FGT_EDEVICE;
+  }
+  double ms[4];
+  int best = -1;
+  int rc = FGT_OK;
+  for (int c = 0; c < 4 && rc == FGT_OK; ++c) {
+    rc = fgt_batch_set_config(plan, fgt::kChunkChoices[c % 2], fgt::kBucketTargets[c / 2]);
+    if (rc == FGT_OK) rc = fgt_batch_eval(plan, x, y, alpha, u, ws, ws_bytes, stream);   // warm-up
+    if (rc != FGT_OK) break;
+    if (hipEventRecord(ev[0], stream) != hipSuccess) rc = FGT_EDEVICE;
+    for (int r = 0; r < 3 && rc == FGT_OK; ++r)
+      rc = fgt_batch_eval(plan, x, y, alpha, u, ws, ws_bytes, stream);
+    float t = 0.f;
+    if (rc == FGT_OK && (hipEventRecord(ev[1], stream) != hipSuccess ||
+                         hipEventSynchronize(ev[1]) != hipSuccess ||
+                         hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess))
+      rc = FGT_EDEVICE;
+    ms[c] = t / 3.0;
+    if (rc == FGT_OK && (best < 0 || ms[c] < ms[best])) best = c;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (rc != FGT_OK || best < 0) return rc != FGT_OK ? rc : FGT_EDEVICE;
+  rc = fgt_batch_set_config(plan, fgt::kChunkChoices[best % 2], fgt::kBucketTargets[best / 2]);
+  if (rc == FGT_OK && cache_path)
+    fgt::cache_store(cache_path, sig, fgt::kChunkChoices[best % 2], fgt::kBucketTargets[best / 2],
+                     ms, 4);
+  return rc;
 }
 
 void fgt_batch_destroy(fgt_batch_t plan) { fgt::batch_free(plan); }
@@ -593,17 +773,8 @@ size_t fgt_eval_batched_workspace_size(int64_t B, const int64_t* x_off, const in
   const fgt::SoeTable* tab = (digits >= 1 && digits <= fgt::max_digits_f64()) ? fgt::choose_table(digits) : nullptr;
   if (!tab || B < 0 || (B > 0 && (!x_off || !y_off))) return 0;
   std::vector<double> ones((size_t)(B > 0 ? B : 1), 1.0);
-  std::vector<fgt::SegInfo> seg;
-  std::vector<fgt::ChunkInfo> chunks;
-  std::vector<fgt::BucketInfo> buckets;
-  std::vector<int64_t> ne_base;
-  std::vector<double> ne_scale;
   fgt::BatchDims d;
-  int max_lg = 0;
-  if (fgt::batch_tables(B, ones.data(), x_off, y_off, R, seg, chunks, buckets, ne_base, ne_scale, d,
-                        max_lg) != FGT_OK)
-    return 0;
-  d.n_modes = tab->n_modes;
+  if (fgt::batch_dims(B, ones.data(), x_off, y_off, R, tab->n_modes, d) != FGT_OK) return 0;
   return fgt::batch_layout(nullptr, d).total;
 }
 

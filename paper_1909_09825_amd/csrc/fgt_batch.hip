@@ -525,9 +525,10 @@ __global__ __launch_bounds__(kBSortThreads) void k_bucket_sort(
 // ---------------------------------------------------------------------------
 // Position of tile point e in the exponential table: one spare entry per
 // chunk staggers the chunks read together by a wave across LDS banks.
-__device__ __forceinline__ int expad(int e) { return e + e / kBChunkPts; }
+template <int CH>
+__device__ __forceinline__ int expad(int e) { return e + e / CH; }
 
-template <int NM, bool REDUCE>
+template <int NM, bool REDUCE, int CH>
 __global__ __launch_bounds__(kBThreads) void k_bscan(
     const double* __restrict__ zs, const uint32_t* __restrict__ ids, int64_t P, int64_t SN,
     int64_t SM, int R, Modes md, const int64_t* __restrict__ ne_base,
@@ -536,12 +537,13 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
     double* __restrict__ tile_fg) {
   constexpr int kWaves = kBThreads / kWave;
   constexpr int kCW = kWave / kBCols;   // chunks per wave (4)
-  static_assert(kBTile == kBThreads, "one tile point per thread in the exponential phase");
+  constexpr int TILE = (kBThreads / kBCols) * CH;   // points per tile
+  static_assert(TILE <= kBThreads, "at most one tile point per thread in the exponential phase");
   __shared__ int64_t s_seg0;
   __shared__ uint32_t s_wflag[kWaves];
-  __shared__ double s_z[kBTile + 1];
-  __shared__ uint32_t s_id[kBTile];
-  __shared__ double s_ex[2 * (kBTile + kBTile / kBChunkPts)];   // padded per chunk: no bank conflicts
+  __shared__ double s_z[TILE + 1];
+  __shared__ uint32_t s_id[TILE];
+  __shared__ double s_ex[2 * (TILE + TILE / CH)];   // padded per chunk: no bank conflicts
   __shared__ double s_wt[kWaves][kBCols][6];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int cl = lane % kBCols;
@@ -550,10 +552,10 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
   const int col = (int)blockIdx.y * kBCols + cl;
   const bool col_ok = col < R;
   const int64_t tile = blockIdx.x;
-  const int64_t t0 = tile * kBTile;
+  const int64_t t0 = tile * TILE;
   const uint32_t src_end = (uint32_t)SN, tgt_end = (uint32_t)(SN + SM);
 
-  for (int e = tid; e < kBTile; e += kBThreads) {
+  for (int e = tid; e < TILE; e += kBThreads) {
     const int64_t p = t0 + e;
     s_z[e + 1] = p < P ? zs[p] : 0.0;
     s_id[e] = p < P ? ids[p] : kPad;
@@ -571,9 +573,9 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
   __syncthreads();
   // Scale of this thread's tile point: transforms starting inside the tile
   // after its first point advance the index.
-  double my_scale;
+  double my_scale = 1.0;
   {
-    const uint32_t code = s_id[tid];
+    const uint32_t code = tid < TILE ? s_id[tid] : kPad;
     const bool flag = tid > 0 && code != kPad && (code & kSegStart);
     const uint64_t m = __ballot(flag);
     const uint32_t incl = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -583,32 +585,32 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
     __syncthreads();
     int64_t sidx = s_seg0 + incl;
     for (int w = 0; w < wave; ++w) sidx += s_wflag[w];
-    my_scale = ne_scale[sidx < K ? sidx : K - 1];
+    if (tid < TILE) my_scale = ne_scale[sidx < K ? sidx : K - 1];
   }
 
-  double b[kBChunkPts];
+  double b[CH];
 #pragma unroll
-  for (int j = 0; j < kBChunkPts; ++j) {
-    const uint32_t code = s_id[chunk * kBChunkPts + j];
+  for (int j = 0; j < CH; ++j) {
+    const uint32_t code = s_id[chunk * CH + j];
     const uint32_t r = code & ~kSegStart;
     b[j] = (code != kPad && r < src_end && col_ok) ? alpha[(int64_t)r * R + col] : 0.0;
   }
-  double acc[kBChunkPts];
+  double acc[CH];
 #pragma unroll
-  for (int j = 0; j < kBChunkPts; ++j) acc[j] = 0.0;
+  for (int j = 0; j < CH; ++j) acc[j] = 0.0;
 
 #pragma unroll 1
   for (int k = 0; k < NM; ++k) {
     // Mode exponentials of the tile's gaps, 0 at the first point of a transform.
     {
-      constexpr int kPer = kBTile / kBThreads;
+      constexpr int kPer = (TILE + kBThreads - 1) / kBThreads;
       double dz[kPer];
       bool cut[kPer];
       double dmax = 0.0;
 #pragma unroll
       for (int q = 0; q < kPer; ++q) {
         const int e = tid + q * kBThreads;
-        const uint32_t code = s_id[e];
+        const uint32_t code = e < TILE ? s_id[e] : kPad;
         cut[q] = code != kPad && (code & kSegStart);
         dz[q] = (code == kPad || cut[q]) ? 0.0 : (s_z[e + 1] - s_z[e]) * my_scale;
         dmax = fmax(dmax, fabs(dz[q]));
@@ -642,8 +644,10 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
         for (int h = 0; h < halvings; ++h) ex = cmul(ex, ex);
         if (cut[q]) ex = {0.0, 0.0};
         const int e = tid + q * kBThreads;
-        s_ex[2 * expad(e)] = ex.re;
-        s_ex[2 * expad(e) + 1] = ex.im;
+        if (e < TILE) {
+          s_ex[2 * expad<CH>(e)] = ex.re;
+          s_ex[2 * expad<CH>(e) + 1] = ex.im;
+        }
       }
     }
     __syncthreads();
@@ -653,9 +657,9 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
     {
       C<double> a = {1.0, 0.0}, f = {0.0, 0.0}, g = {0.0, 0.0};
 #pragma unroll
-      for (int j = 0; j < kBChunkPts; ++j) {
-        const int e = chunk * kBChunkPts + j;
-        const C<double> ex = {s_ex[2 * expad(e)], s_ex[2 * expad(e) + 1]};
+      for (int j = 0; j < CH; ++j) {
+        const int e = chunk * CH + j;
+        const C<double> ex = {s_ex[2 * expad<CH>(e)], s_ex[2 * expad<CH>(e) + 1]};
         a = cmul(a, ex);
         f = cfma(ex, f, C<double>{b[j], 0.0});
         g.re = fma(b[j], a.re, g.re);
@@ -737,17 +741,17 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
       const double om_re = md.om_re[k], om_im = md.om_im[k];
       C<double> hh = cf;
 #pragma unroll
-      for (int j = 0; j < kBChunkPts; ++j) {
-        const int e = chunk * kBChunkPts + j;
-        const C<double> ex = {s_ex[2 * expad(e)], s_ex[2 * expad(e) + 1]};
+      for (int j = 0; j < CH; ++j) {
+        const int e = chunk * CH + j;
+        const C<double> ex = {s_ex[2 * expad<CH>(e)], s_ex[2 * expad<CH>(e) + 1]};
         hh = cfma(ex, hh, C<double>{b[j], 0.0});
         acc[j] = fma(om_re, hh.re, fma(-om_im, hh.im, acc[j]));
       }
       C<double> g = cb;
 #pragma unroll
-      for (int j = kBChunkPts - 1; j >= 0; --j) {
-        const int e = chunk * kBChunkPts + j;
-        const C<double> ex = {s_ex[2 * expad(e)], s_ex[2 * expad(e) + 1]};
+      for (int j = CH - 1; j >= 0; --j) {
+        const int e = chunk * CH + j;
+        const C<double> ex = {s_ex[2 * expad<CH>(e)], s_ex[2 * expad<CH>(e) + 1]};
         acc[j] = fma(om_re, g.re, fma(-om_im, g.im, acc[j]));
         g = cmul(ex, cadd(g, C<double>{b[j], 0.0}));
       }
@@ -757,30 +761,40 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
 
   if (!REDUCE && col_ok) {
 #pragma unroll
-    for (int j = 0; j < kBChunkPts; ++j) {
-      const uint32_t code = s_id[chunk * kBChunkPts + j];
+    for (int j = 0; j < CH; ++j) {
+      const uint32_t code = s_id[chunk * CH + j];
       const uint32_t r = code & ~kSegStart;
       if (code != kPad && r >= src_end && r < tgt_end) u[(int64_t)(r - src_end) * R + col] = acc[j];
     }
   }
 }
 
-template <int NM>
+template <int NM, int CH>
 hipError_t batch_scan(const BatchDims& d, const Modes& md, const int64_t* ne_base,
                       const double* ne_scale, const double* alpha, double* u, const BatchWork& w,
                       hipStream_t s) {
-  const dim3 grid((unsigned)d.tiles, (unsigned)((d.R + kBCols - 1) / kBCols));
-  hipLaunchKernelGGL((k_bscan<NM, true>), grid, dim3(kBThreads), 0, s, w.zs, w.ids, d.P, d.SN,
+  constexpr int TILE = (kBThreads / kBCols) * CH;
+  const int64_t tiles = (d.P + TILE - 1) / TILE;
+  const dim3 grid((unsigned)tiles, (unsigned)((d.R + kBCols - 1) / kBCols));
+  hipLaunchKernelGGL((k_bscan<NM, true, CH>), grid, dim3(kBThreads), 0, s, w.zs, w.ids, d.P, d.SN,
                      d.SM, d.R, md, ne_base, ne_scale, d.K, alpha, (const double*)nullptr,
                      (double*)nullptr, w.tile_a, w.tile_fg);
   const int nq = NM * d.R;
-  hipError_t e = launch_carries<double>(BatchMaps<double>{w.tile_a, w.tile_fg, NM, d.R}, d.tiles,
+  hipError_t e = launch_carries<double>(BatchMaps<double>{w.tile_a, w.tile_fg, NM, d.R}, tiles,
                                         nq, w.chunk_agg, w.chunk_carry, w.carry, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_bscan<NM, false>), grid, dim3(kBThreads), 0, s, w.zs, w.ids, d.P, d.SN,
+  hipLaunchKernelGGL((k_bscan<NM, false, CH>), grid, dim3(kBThreads), 0, s, w.zs, w.ids, d.P, d.SN,
                      d.SM, d.R, md, ne_base, ne_scale, d.K, alpha, (const double*)w.carry, u,
                      (double*)nullptr, (double*)nullptr);
   return hipGetLastError();
+}
+
+template <int NM>
+hipError_t batch_scan_chunk(int chunk, const BatchDims& d, const Modes& md, const int64_t* ne_base,
+                            const double* ne_scale, const double* alpha, double* u,
+                            const BatchWork& w, hipStream_t s) {
+  return chunk == 8 ? batch_scan<NM, 8>(d, md, ne_base, ne_scale, alpha, u, w, s)
+                    : batch_scan<NM, 16>(d, md, ne_base, ne_scale, alpha, u, w, s);
 }
 
 __global__ void k_clear_words(uint32_t* __restrict__ p, int n) {
@@ -826,12 +840,15 @@ BatchWork batch_layout(void* base, const BatchDims& d) {
   return w;
 }
 
-hipError_t batch_eval_launch(const BatchDims& d, const Modes& md, double s_allow,
-                             const SegInfo* seg, const ChunkInfo* chunks,
-                             const BucketInfo* buckets, const int64_t* ne_base,
-                             const double* ne_scale, int max_nb_log2, const double* x,
-                             const double* y, const double* alpha, double* u,
-                             const BatchWork& w, hipStream_t s) {
+hipError_t batch_eval_launch(const BatchDims& d, const BatchTables& t, const Modes& md,
+                             double s_allow, int chunk, const double* x, const double* y,
+                             const double* alpha, double* u, const BatchWork& w, hipStream_t s) {
+  const SegInfo* seg = t.seg;
+  const ChunkInfo* chunks = t.chunks;
+  const BucketInfo* buckets = t.buckets;
+  const int64_t* ne_base = t.ne_base;
+  const double* ne_scale = t.ne_scale;
+  const int max_nb_log2 = t.max_nb_log2;
   hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, s, w.status, 64);
   if (d.P == 0) return hipGetLastError();
   hipLaunchKernelGGL(k_seg_minmax, dim3((unsigned)d.B), dim3(256), 0, s, seg, x, y, w.lo, w.hi,
@@ -848,7 +865,7 @@ hipError_t batch_eval_launch(const BatchDims& d, const Modes& md, double s_allow
                        4 * nb_max * sizeof(uint32_t), s, seg, chunks, x, y, (const double*)w.lo,
                        (const double*)w.hi, (const uint32_t*)w.offs, w.ids_tmp);
   }
-  hipLaunchKernelGGL(k_bucket_sort, dim3((unsigned)d.n_buckets), dim3(kBSortThreads), 0, s, seg,
+  hipLaunchKernelGGL(k_bucket_sort, dim3((unsigned)t.n_buckets), dim3(kBSortThreads), 0, s, seg,
                      buckets, x, y, (const double*)w.lo, (const double*)w.hi,
                      (const uint32_t*)w.bstart, (const uint32_t*)w.bsize,
                      (const uint32_t*)w.ids_tmp, w.qbuf[0], w.qbuf[1], w.ibuf[0], w.ibuf[1],
@@ -856,13 +873,13 @@ hipError_t batch_eval_launch(const BatchDims& d, const Modes& md, double s_allow
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (md.n) {
-    case 1: return batch_scan<1>(d, md, ne_base, ne_scale, alpha, u, w, s);
-    case 2: return batch_scan<2>(d, md, ne_base, ne_scale, alpha, u, w, s);
-    case 3: return batch_scan<3>(d, md, ne_base, ne_scale, alpha, u, w, s);
-    case 4: return batch_scan<4>(d, md, ne_base, ne_scale, alpha, u, w, s);
-    case 5: return batch_scan<5>(d, md, ne_base, ne_scale, alpha, u, w, s);
-    case 6: return batch_scan<6>(d, md, ne_base, ne_scale, alpha, u, w, s);
-    case 7: return batch_scan<7>(d, md, ne_base, ne_scale, alpha, u, w, s);
+    case 1: return batch_scan_chunk<1>(chunk, d, md, ne_base, ne_scale, alpha, u, w, s);
+    case 2: return batch_scan_chunk<2>(chunk, d, md, ne_base, ne_scale, alpha, u, w, s);
+    case 3: return batch_scan_chunk<3>(chunk, d, md, ne_base, ne_scale, alpha, u, w, s);
+    case 4: return batch_scan_chunk<4>(chunk, d, md, ne_base, ne_scale, alpha, u, w, s);
+    case 5: return batch_scan_chunk<5>(chunk, d, md, ne_base, ne_scale, alpha, u, w, s);
+    case 6: return batch_scan_chunk<6>(chunk, d, md, ne_base, ne_scale, alpha, u, w, s);
+    case 7: return batch_scan_chunk<7>(chunk, d, md, ne_base, ne_scale, alpha, u, w, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -219,17 +219,17 @@ hipError_t presorted_points(const Workspace& w, const T* x, const T* alpha, int6
 // counting per chunk of kBChunk points), then every bucket is radix-sorted in
 // LDS (kBucketMax points at most; larger buckets take a slower block-global path).
 constexpr int kBChunk = 4096;
-constexpr int kBucketTarget = 2048;
 constexpr int kBucketMax = 4096;
 constexpr int kBSortThreads = 512;
 constexpr int kBSortItems = kBucketMax / kBSortThreads;   // 8
 constexpr int kMaxBucketLog2 = 12;
-// Scan: tiles of kBTile sorted points; a wave holds 4 chunks x 16 columns,
-// a lane runs kBChunkPts consecutive points of one column.
+// Scan: a wave holds 4 chunks x 16 columns, a lane runs consecutive points
+// of one column.
 constexpr int kBCols = 16;
 constexpr int kBThreads = 512;
-constexpr int kBChunkPts = 16;
-constexpr int kBTile = (kBThreads / kBCols) * kBChunkPts;   // 512
+// Points per lane and column: 8 or 16 (chosen per batch by the autotuner);
+// a tile holds (kBThreads / kBCols) chunks.
+constexpr int kBTileMin = (kBThreads / kBCols) * 8;   // 256
 // Bit of a sorted id that marks the first point of a transform.
 constexpr uint32_t kSegStart = 0x80000000u;
 
@@ -275,6 +275,17 @@ struct BatchWork {
   size_t total;
 };
 
+// Device tables of a batch plan for one bucket size.
+struct BatchTables {
+  const SegInfo* seg;
+  const ChunkInfo* chunks;
+  const BucketInfo* buckets;
+  const int64_t* ne_base;
+  const double* ne_scale;
+  int64_t n_buckets;
+  int max_nb_log2;
+};
+
 struct BatchDims {
   int64_t B, P, SN, SM, n_chunks, n_buckets, n_counts, tiles;
   int64_t K;              // transforms with at least one point
@@ -283,13 +294,11 @@ struct BatchDims {
 
 BatchWork batch_layout(void* base, const BatchDims& d);
 
-// ne_base / ne_scale: first sorted position and 1/sqrt(delta) of each transform
-// with at least one point, in order.
-hipError_t batch_eval_launch(const BatchDims& d, const Modes& md, double s_allow,
-                             const SegInfo* seg, const ChunkInfo* chunks,
-                             const BucketInfo* buckets, const int64_t* ne_base,
-                             const double* ne_scale, int max_nb_log2, const double* x,
-                             const double* y, const double* alpha, double* u,
-                             const BatchWork& w, hipStream_t s);
+// The whole batch: sort, then the scan with `chunk` (8 or 16) points per lane.
+// d sizes the workspace (maxima over the tunable choices); t holds the tables
+// of the chosen bucket size.
+hipError_t batch_eval_launch(const BatchDims& d, const BatchTables& t, const Modes& md,
+                             double s_allow, int chunk, const double* x, const double* y,
+                             const double* alpha, double* u, const BatchWork& w, hipStream_t s);
 
 }  // namespace fgt

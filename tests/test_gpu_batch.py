@@ -199,3 +199,35 @@ def test_batch_4096_transforms_16_columns():
         e1, _ = check_transform(bt, u, int(b), 6, targets=ti, recurrence=False)
         worst = max(worst, e1)
     say(f"   64 transforms x 256 targets x 16 columns: worst O1 err / E_n = {worst:.3e}")
+
+
+def test_batch_tuner_choices_agree_and_cache(tmp_path):
+    """Every kernel choice gives the same transform (to rounding); the tuner
+    picks one of them and records it in the JSON cache, which a second plan
+    of the same shape reads back."""
+    bt = make_batch([(3000, 2000), (0, 10), (9000, 11000), (64, 64), (40000, 30000)],
+                    [1e-3, 1e-2, 1e-5, 0.1, 1e-4], R=16, seed=17)
+    say("[gpu] batch tuner: 4 choices, then tune with a cache")
+    bp = fgt.batch_plan(bt.delta, 6, bt.x_off, bt.y_off, 16)
+    X, Y = to_dev(bt.x, torch.float64), to_dev(bt.y, torch.float64)
+    A = to_dev(bt.alpha, torch.float64)
+    ws = fgt.batch_workspace(bp, X.device)
+    outs = {}
+    for chunk in (8, 16):
+        for bucket in (1024, 2048):
+            bp.set_config(chunk, bucket)
+            outs[(chunk, bucket)] = fgt.eval_batch(X, Y, A, bp, ws=ws).cpu().numpy()
+    ref = outs[(16, 2048)]
+    scale = np.abs(bt.alpha).sum(axis=0).max()
+    for k, v in outs.items():
+        assert np.max(np.abs(v - ref)) <= 1e-12 * scale, k
+    with pytest.raises(fgt.FGTError):
+        bp.set_config(12, 2048)
+    cache = str(tmp_path / "tune.json")
+    cfg = bp.tune(X, Y, A, ws=ws, cache=cache)
+    assert cfg in outs
+    text = open(cache).read()
+    assert "gfx950:" in text and f'"chunk": {cfg[0]}' in text
+    bp2 = fgt.batch_plan(bt.delta, 6, bt.x_off, bt.y_off, 16)
+    bp2.set_config(8 if cfg[0] == 16 else 16, 1024 if cfg[1] == 2048 else 2048)
+    assert bp2.tune(X, Y, A, ws=ws, cache=cache) == cfg
