@@ -48,15 +48,15 @@ __global__ __launch_bounds__(kWave) void k_adj_reduce(const void* keys0, const v
                                                       T* __restrict__ agg,
                                                       int32_t* __restrict__ tile_k) {
   constexpr int NQ = 2 * NM;
-  const void* keys = pass->final_buf ? keys1 : keys0;
+  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
   const int lane = threadIdx.x;
   const int64_t tile = blockIdx.x;
   const int64_t t0 = tile * kScanTile;
   const int n = (int)((P - t0) < kScanTile ? (P - t0) : kScanTile);
   const uint32_t M = (uint32_t)(P - N);
-  const T zfirst = key_value<T>(keys, t0);
-  const T zprev = t0 > 0 ? key_value<T>(keys, t0 - 1) : zfirst;
-  const T zlast = key_value<T>(keys, t0 + n - 1);
+  const T zfirst = keys(t0);
+  const T zprev = t0 > 0 ? keys(t0 - 1) : zfirst;
+  const T zlast = keys(t0 + n - 1);
   const T c = zprev + (zlast - zprev) * T(0.5);
   const T hf = zlast - c;
   const T hg = c - zprev;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kWave) void k_adj_reduce(const void* keys0, const v
       mu1[m] = T(0);
     }
     for (int e = lane; e < n; e += kWave) {
-      const T s = key_value<T>(keys, t0 + e) - c;
+      const T s = keys(t0 + e) - c;
       const T wt = gather(e);
       bt[t0 + e] = wt;
       T p0 = b[t0 + e], p1 = wt;
@@ -158,9 +158,9 @@ __global__ __launch_bounds__(kWave) void k_adj_reduce(const void* keys0, const v
     const int k = q % NM;
     const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
     Seg<T> s = seg_identity<T>();
-    T zl = e0 == 0 ? zprev : (cnt > 0 ? key_value<T>(keys, t0 + e0 - 1) : zlast);
+    T zl = e0 == 0 ? zprev : (cnt > 0 ? keys(t0 + e0 - 1) : zlast);
     for (int j = 0; j < cnt; ++j) {
-      const T zj = key_value<T>(keys, t0 + e0 + j);
+      const T zj = keys(t0 + e0 + j);
       const C<T> ex = exp_neg_general<T>(tr, ti, zj - zl);
       const T w = ch ? gather(e0 + j) : b[t0 + e0 + j];
       s.a = cmul(s.a, ex);
@@ -169,8 +169,8 @@ __global__ __launch_bounds__(kWave) void k_adj_reduce(const void* keys0, const v
     }
     C<T> gg = {T(0), T(0)};
     for (int j = cnt - 1; j >= 0; --j) {
-      const T zj = key_value<T>(keys, t0 + e0 + j);
-      const T zb = (e0 + j == 0) ? zprev : key_value<T>(keys, t0 + e0 + j - 1);
+      const T zj = keys(t0 + e0 + j);
+      const T zb = (e0 + j == 0) ? zprev : keys(t0 + e0 + j - 1);
       const C<T> ex = exp_neg_general<T>(tr, ti, zj - zb);
       const T w = ch ? gather(e0 + j) : b[t0 + e0 + j];
       gg = cmul(ex, cadd(gg, C<T>{w, T(0)}));
@@ -258,7 +258,7 @@ union AdjFastLds {
 
 // Loads this thread's share of the tile into LDS (coalesced), all loads first.
 template <class T>
-__device__ __forceinline__ void stage_tile(Staged2<T>& st, const void* keys, const T* b,
+__device__ __forceinline__ void stage_tile(Staged2<T>& st, const KeyView<T>& keys, const T* b,
                                            const T* bt, const uint32_t* ids, int64_t t0,
                                            int64_t P) {
   constexpr int R = kScanTile / kScanThreads;
@@ -269,7 +269,7 @@ __device__ __forceinline__ void stage_tile(Staged2<T>& st, const void* keys, con
   for (int r = 0; r < R; ++r) {
     const int64_t p = t0 + tid + r * kScanThreads;
     const bool in = p < P;
-    zr[r] = in ? key_value<T>(keys, p) : T(0);
+    zr[r] = in ? keys(p) : T(0);
     br[r] = in ? b[p] : T(0);
     gr[r] = in ? bt[p] : T(0);
     ir[r] = in ? ids[p] : kNoSlot;
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kScanThreads) void k_adj_final_fast(
   const int64_t tile = blockIdx.x;
   const int K = tile_k[tile];
   if (K < 0 || K > kAdjMoments) return;
-  const void* keys = pass->final_buf ? keys1 : keys0;
+  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
   __shared__ AdjFastLds<T> lds;
   __shared__ T mtot[2][kAdjMoments + 1][kScanWaves];
   __shared__ double wsum[kScanWaves];
@@ -308,11 +308,11 @@ __global__ __launch_bounds__(kScanThreads) void k_adj_final_fast(
   const int n = (int)((P - t0) < kScanTile ? (P - t0) : kScanTile);
 
   stage_tile(lds.st, keys, b, bt, ids, t0, P);
-  const T zfirst = key_value<T>(keys, t0);
-  const T zprev = t0 > 0 ? key_value<T>(keys, t0 - 1) : zfirst;
-  const T zlast = key_value<T>(keys, t0 + n - 1);
+  const T zfirst = keys(t0);
+  const T zprev = t0 > 0 ? keys(t0 - 1) : zfirst;
+  const T zlast = keys(t0 + n - 1);
   const T c = zprev + (zlast - zprev) * T(0.5);
-  const double zc = 0.5 * ((double)key_value<T>(keys, 0) + (double)key_value<T>(keys, P - 1));
+  const double zc = 0.5 * ((double)keys(0) + (double)keys(P - 1));
   __syncthreads();
 
   const int e0 = tid * kScanChunk;
@@ -498,7 +498,7 @@ __global__ __launch_bounds__(kScanThreads) void k_adj_final(
     const int K = tile_k[blockIdx.x];
     if (K >= 0 && K <= kAdjMoments) return;
   }
-  const void* keys = pass->final_buf ? keys1 : keys0;
+  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
   __shared__ Staged2<T> st;
   __shared__ Seg<T> wtot[2][kScanWaves][2];   // per channel and wave: forward, backward totals
   __shared__ double wsum[kScanWaves];
@@ -510,8 +510,8 @@ __global__ __launch_bounds__(kScanThreads) void k_adj_final(
   const int n = (int)((P - t0) < kScanTile ? (P - t0) : kScanTile);
 
   stage_tile(st, keys, b, bt, ids, t0, P);
-  T zprev = t0 > 0 ? key_value<T>(keys, t0 - 1) : T(0);
-  const double zc = 0.5 * ((double)key_value<T>(keys, 0) + (double)key_value<T>(keys, P - 1));
+  T zprev = t0 > 0 ? keys(t0 - 1) : T(0);
+  const double zc = 0.5 * ((double)keys(0) + (double)keys(P - 1));
   __syncthreads();
 
   const int e0 = tid * kScanChunk;

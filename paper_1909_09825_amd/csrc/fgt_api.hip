@@ -52,7 +52,7 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   // The region cleared at the start of each call is contiguous: status word
   // (always at offset 0), histograms, tile counters and the first look-back buffer.
   w.status = (uint32_t*)take(sizeof(uint32_t) * 64);
-  w.maxabs = (unsigned long long*)take(sizeof(unsigned long long));
+  w.range = (unsigned long long*)take(2 * sizeof(unsigned long long));
   w.hist = (uint32_t*)take(sizeof(uint32_t) * digits * kRadix);
   w.tile_ctr = (uint32_t*)take(sizeof(uint32_t) * 8);
   w.lookback[0] = (uint64_t*)take(sizeof(uint64_t) * (size_t)w.sort_tiles * kRadix);
@@ -119,8 +119,12 @@ void make_modes(const SoeTable* tab, double delta, int dtype, Modes* m) {
   // +|x - y| (continued through the same exponentials); with s = |x - y| /
   // sqrt(delta) the change is |Re sum omega (e^{tau0 s} - e^{-tau0 s})| <=
   // 2 |Re sum omega tau0| s + (1/3) sum |omega| |tau0|^3 s^3 cosh(max|tau0| s).
-  // s_w makes this at most 1e-6 E_n, so the result stays within
-  // (1 + 1e-6) E_n sum|alpha| of the Gauss transform.
+  // With IEEE order keys s_w makes this at most 1e-6 E_n, so the result stays
+  // within (1 + 1e-6) E_n sum|alpha| of the Gauss transform.  The FP64 grid
+  // code splits that allowance: unordered pairs take 0.5e-6 E_n, and moving
+  // each point by at most code_tol the other half, since a shift e of both
+  // ends changes a term by at most |alpha| (max|G'| + E'_n) 2 e / sqrt(delta)
+  // with max|G'| = 2^{-1/2} e^{-1/2} for G(s) = exp(-s^2/4).
   {
     double slope = 0.0, c3 = 0.0, tmax = 0.0;
     for (int k = 0; k < tab->n_modes; ++k) {
@@ -130,14 +134,21 @@ void make_modes(const SoeTable* tab, double delta, int dtype, Modes* m) {
       if (ta > tmax) tmax = ta;
     }
     slope = fabs(slope);
-    const double target = 1e-6 * tab->err_bound;
-    double lo = 0.0, hi = 1.0;
-    for (int it = 0; it < 200; ++it) {
-      const double s = 0.5 * (lo + hi);
-      const double b = 2.0 * slope * s + c3 * s * s * s * cosh(tmax * s) / 3.0;
-      if (b <= target) lo = s; else hi = s;
-    }
-    m->key_width = lo * sqrt(delta);
+    auto width = [&](double fraction) {
+      const double target = fraction * tab->err_bound;
+      double lo = 0.0, hi = 1.0;
+      for (int it = 0; it < 200; ++it) {
+        const double s = 0.5 * (lo + hi);
+        const double b = 2.0 * slope * s + c3 * s * s * s * cosh(tmax * s) / 3.0;
+        if (b <= target) lo = s; else hi = s;
+      }
+      return lo * sqrt(delta);
+    };
+    m->key_width = width(1e-6);
+    m->sort.key_width = m->key_width;
+    m->sort.key_width_q = width(0.5e-6);
+    const double max_dg = sqrt(0.5) * exp(-0.5);
+    m->sort.code_tol = 0.25e-6 * tab->err_bound * sqrt(delta) / (max_dg + tab->deriv_err_bound);
   }
   for (int k = 0; k < tab->n_modes; ++k) {
     double cr = 1.0, ci = 0.0;
@@ -193,7 +204,7 @@ hipError_t forward(const fgt_plan_s* plan, const Workspace& w, const void* x, in
   const int64_t P = M + N;
   hipError_t e = hipSuccess;
   if (sort) {
-    e = sort_points<T>(w, (const T*)x, M, (const T*)y, (const T*)alpha, N, plan->modes.key_width,
+    e = sort_points<T>(w, (const T*)x, M, (const T*)y, (const T*)alpha, N, plan->modes.sort,
                        s, tl);
   } else {
     e = gather_strengths<T>(w, P, 0u, (uint32_t)N, (const T*)alpha, (T*)w.b, s);
@@ -212,7 +223,7 @@ hipError_t backward(const fgt_plan_s* plan, const Workspace& w, const void* x, i
   if (sort) {
     Timeline none;
     const hipError_t e = sort_points<T>(w, (const T*)x, M, (const T*)y, (const T*)alpha, N,
-                                        plan->modes.key_width, s, &none);
+                                        plan->modes.sort, s, &none);
     if (e != hipSuccess) return e;
   }
   return adjoint_points<T>(w, plan->modes, M, N, (const T*)g, (T*)dx, (T*)dalpha, (T*)dy,
@@ -365,7 +376,7 @@ int fgt_eval_self(fgt_plan_t plan, const void* x, int64_t N, const void* alpha, 
     e = (flags & FGT_PRESORTED)
             ? fgt::presorted_points<double>(w, (const double*)x, (const double*)alpha, N, stream)
             : fgt::sort_points<double>(w, nullptr, 0, (const double*)x, (const double*)alpha, N,
-                                       plan->modes.key_width, stream, &none);
+                                       plan->modes.sort, stream, &none);
     if (e == hipSuccess)
       e = fgt::scan_points<double>(w, plan->modes, N,
                                    (flags & FGT_PRESORTED) ? (const double*)alpha : (const double*)w.b,
@@ -375,7 +386,7 @@ int fgt_eval_self(fgt_plan_t plan, const void* x, int64_t N, const void* alpha, 
     e = (flags & FGT_PRESORTED)
             ? fgt::presorted_points<float>(w, (const float*)x, (const float*)alpha, N, stream)
             : fgt::sort_points<float>(w, nullptr, 0, (const float*)x, (const float*)alpha, N,
-                                      plan->modes.key_width, stream, &none);
+                                      plan->modes.sort, stream, &none);
     if (e == hipSuccess)
       e = fgt::scan_points<float>(w, plan->modes, N,
                                    (flags & FGT_PRESORTED) ? (const float*)alpha : (const float*)w.b,

@@ -89,12 +89,6 @@ struct InvFact {
 };
 __constant__ constexpr InvFact kInvFact{};
 
-template <class T>
-__device__ __forceinline__ T key_value(const void* keys, int64_t p) {
-  using K = typename KeyOf<T>::type;
-  return from_key(((const K*)keys)[p]);
-}
-
 // ---------------------------------------------------------------------------
 // Carries over tiles, for every scan q (one per mode; q = channel * modes +
 // mode when two strength channels share the sweeps).  CF[t] = forward value

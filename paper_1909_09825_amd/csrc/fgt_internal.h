@@ -27,6 +27,16 @@ constexpr int kMomentMax = 20;
 // |tau_k|, max_k |tau_k|, and the Taylor thresholds of the plan's precision:
 // degree D is enough for exp(-w) when |w| <= taylor_thr[D], i.e.
 // taylor_thr[D]^{D+1} / (D+1)! equals the unit roundoff.
+// Sort resolution.  With IEEE order keys, coordinates closer than key_width
+// may be left unordered; with the FP64 grid code (Codec<double>) the points
+// may also move by up to code_tol, and both take half of the allowance:
+// key_width_q, code_tol.
+struct SortRes {
+  double key_width;
+  double key_width_q;
+  double code_tol;
+};
+
 struct Modes {
   int n;
   double tau_re[FGT_MAX_MODES], tau_im[FGT_MAX_MODES];
@@ -35,6 +45,7 @@ struct Modes {
   double tau_abs_max;
   double taylor_thr[kTaylorMax + 1];
   double key_width;   // sort resolution in coordinate units (see fgt_plan)
+  SortRes sort;
   // Largest gap whose exponential the degree-kTaylorMax polynomial serves:
   // taylor_thr[kTaylorMax] / |tau_k|.
   double dz_lim[FGT_MAX_MODES];
@@ -70,7 +81,7 @@ constexpr int kWave = 64;
 constexpr int kSortThreads = 512;
 constexpr int kSortWaves = kSortThreads / kWave;
 constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per tile
+constexpr int kSortTile = kSortThreads * kSortItems;   // 8192 keys per tile
 constexpr int kRadix = 256;
 constexpr int kHistBlocks = 2048;
 
@@ -113,6 +124,117 @@ __device__ __forceinline__ float from_key(uint32_t k) {
   return __uint_as_float(b);
 }
 
+__device__ __forceinline__ uint64_t bits_of(double z) {
+  return (uint64_t)__double_as_longlong(z);
+}
+__device__ __forceinline__ uint32_t bits_of(float z) { return __float_as_uint(z); }
+
+// Sort keys as the radix passes see them.  FP32 coordinates keep their IEEE
+// order keys.  FP64 coordinates are, where that loses nothing that matters,
+// coded as fixed-point offsets on a power-of-two grid g sized to the range
+// [lo, hi] of the call's points (hi - lo < 2^61 g): the key bits are spent on
+// the occupied interval, and more low digits fall below the sort resolution
+// and are skipped.  Coordinates on the grid (every |z| >= 2^-8 of the range's
+// power of two, or all of them when the range sits far from 0) decode
+// exactly; smaller ones are truncated by less than g, and the code is used
+// only when such a shift is within the plan's tolerance (else IEEE keys).
+template <class T> struct Codec;
+template <> struct Codec<double> {
+  double L;        // offset subtracted before scaling (exact by Sterbenz), or 0
+  double g, inv_g; // grid step 2^e and its inverse
+  int64_t F;       // grid index of the range's aligned start when L = 0
+  int32_t quant;   // 0: IEEE order keys
+  static constexpr int64_t kMax = int64_t(1) << 61;
+  __device__ __forceinline__ uint64_t encode(double z) const {
+    if (!quant) return to_key(z);
+    double t = (z - L) * inv_g;                 // exact for grid points
+    const double t0 = (double)F;                // exact (a multiple of 2^60)
+    t = t > t0 ? t : t0;                        // (NaN lands here too)
+    t = t < t0 + (double)kMax ? t : t0 + (double)kMax;
+    return (uint64_t)((int64_t)t - F);
+  }
+  __device__ __forceinline__ double decode(uint64_t q) const {
+    if (!quant) return from_key(q);
+    return fma((double)((int64_t)q + F), g, L);
+  }
+};
+template <> struct Codec<float> {
+  __device__ __forceinline__ uint32_t encode(float z) const { return to_key(z); }
+  __device__ __forceinline__ float decode(uint32_t k) const { return from_key(k); }
+};
+
+// Code for points whose smallest and largest IEEE order keys are kmin, kmax.
+// With span = hi - lo < 2^E the grid is g = 2^(E-60) and the range starts at
+// lo_a = floor(lo / 2^E) 2^E, so every key is below 2^61.  If |lo_a| >= 2^(E+2)
+// all points share lo_a's sign and lie within a factor 2 of it: z - lo_a is
+// exact and a multiple of g.  Otherwise keys are z / g (exact power-of-two
+// scaling, |z / g| < 5 2^60) less lo_a / g; points with |z| < 2^(E-8) may lie off
+// the grid and move by less than g, which must not exceed code_tol.
+// Degenerate ranges (non-finite, all equal, extreme exponents) keep IEEE keys.
+__device__ __forceinline__ Codec<double> make_codec(uint64_t kmin, uint64_t kmax,
+                                                    double code_tol) {
+  Codec<double> c{0.0, 0.0, 0.0, 0, 0};
+  const double lo = from_key(kmin), hi = from_key(kmax);
+  if (!(isfinite(lo) && isfinite(hi) && hi > lo)) return c;
+  const double span = hi - lo;
+  if (!isfinite(span)) return c;
+  int E = 0;
+  (void)frexp(span, &E);                        // span < 2^E
+  if (E > 1000 || E < -900) return c;
+  const double pE = ldexp(1.0, E);
+  double lo_a = floor(lo / pE) * pE;
+  if (lo_a > lo) lo_a -= pE;
+  const double g = ldexp(1.0, E - 60);
+  if (fabs(lo_a) >= 4.0 * pE) {
+    c.L = lo_a;
+    c.F = 0;
+  } else {
+    const double small = ldexp(1.0, E - 8);
+    if (lo < small && hi > -small && !(g <= code_tol)) return c;
+    c.L = 0.0;
+    c.F = (int64_t)(lo_a * ldexp(1.0, 60 - E));
+  }
+  c.g = g;
+  c.inv_g = ldexp(1.0, 60 - E);
+  c.quant = 1;
+  return c;
+}
+
+struct PassInfo {
+  int32_t run[8];     // 1 if radix pass d moves data
+  int32_t src[8];     // 0/1: key buffer it reads, 2: the raw coordinates
+  int32_t final_buf;  // buffer that holds the sorted keys at the end
+  int32_t last_pass;  // the last pass that runs; it also writes strengths and the final ids
+  int32_t skipped_low;  // low digits left unsorted (below the plan's key resolution)
+  int32_t code_quant;   // FP64 key code of the sorted keys (Codec<double>)
+  int64_t code_F;
+  double code_L, code_g, code_inv_g;
+};
+
+template <class T>
+__device__ __forceinline__ Codec<T> codec_of(const PassInfo* pass) {
+  if constexpr (sizeof(T) == 8) {
+    return Codec<double>{pass->code_L, pass->code_g, pass->code_inv_g, pass->code_F,
+                         pass->code_quant};
+  } else {
+    (void)pass;
+    return Codec<float>{};
+  }
+}
+
+// The sorted coordinates left by the last sort (its last pass stores them in
+// place of the keys).
+template <class T>
+struct KeyView {
+  const T* z;
+  __device__ __forceinline__ T operator()(int64_t p) const { return z[p]; }
+};
+template <class T>
+__device__ __forceinline__ KeyView<T> key_view(const void* keys0, const void* keys1,
+                                               const PassInfo* pass) {
+  return KeyView<T>{(const T*)(pass->final_buf ? keys1 : keys0)};
+}
+
 // Merged index given to padding past the last point (never an output).
 constexpr uint32_t kNoSlot = 0xffffffffu;
 
@@ -124,17 +246,9 @@ constexpr uint32_t kStatusUnsorted = 4u;
 // ---------------------------------------------------------------------------
 // Workspace layout (all offsets 256-byte aligned).
 // ---------------------------------------------------------------------------
-struct PassInfo {
-  int32_t run[8];     // 1 if radix pass d moves data
-  int32_t src[8];     // 0/1: key buffer it reads, 2: the raw coordinates
-  int32_t final_buf;  // buffer that holds the sorted keys at the end
-  int32_t last_pass;  // the last pass that runs; it also writes strengths and the final ids
-  int32_t skipped_low;  // low digits left unsorted (below the plan's key resolution)
-  int32_t pad[5];
-};
 
 struct Workspace {
-  void* keys[2];
+  void* keys[2];         // [P] each: radix keys; the last pass leaves the sorted coordinates
   uint32_t* idx[2];
   void* b;               // [P] strength of each sorted point (alpha_j for a source, 0 for a target)
   uint32_t* ids;         // [P] merged index of each sorted point: j < N source j, else target j - N
@@ -142,7 +256,7 @@ struct Workspace {
                          //     sources); shares the permutation buffers, which are dead after the sort
   double* tile_part;     // [scan_tiles] per-tile parts of the delta-gradient sum
   uint32_t* status;      // [1] at offset 0, zeroed per call
-  unsigned long long* maxabs;  // [1] largest |coordinate| as ordered bits, zeroed per call
+  unsigned long long* range;   // [2] ~(smallest key), largest key (IEEE order), zeroed per call
   uint32_t* hist;        // [digits][256], zeroed per call
   uint32_t* tile_ctr;    // [8], zeroed per call
   uint64_t* lookback[2]; // [sort_tiles][256]; [0] zeroed per call, each pass clears the other
@@ -181,11 +295,12 @@ void make_modes(const SoeTable* tab, double delta, int dtype, Modes* m);
 Workspace layout(void* base, int64_t P, int esz, int n_modes);
 
 // Kernel launch sequences (defined in the .hip files).
-// key_width: coordinate differences below it may be left unordered (see
-// the plan's key resolution); 0 sorts every digit.
+// res: coordinate differences below the resolution may be left unordered;
+// zero widths sort every digit, a zero code_tol keeps IEEE keys wherever the
+// grid code would move a point.
 template <class T>
 hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, const T* alpha,
-                       int64_t N, double key_width, hipStream_t s, Timeline* tl);
+                       int64_t N, const SortRes& res, hipStream_t s, Timeline* tl);
 // Scan of strengths `b` ([P], sorted order) over the sorted keys; writes what
 // `out` asks for.
 template <class T>

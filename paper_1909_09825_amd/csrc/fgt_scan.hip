@@ -46,14 +46,14 @@ __global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void*
                                                   const T* __restrict__ bs, int64_t P, Modes md,
                                                   T* __restrict__ agg,
                                                   int32_t* __restrict__ tile_k) {
-  const void* keys = pass->final_buf ? keys1 : keys0;
+  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
   const int lane = threadIdx.x;
   const int64_t tile = blockIdx.x;
   const int64_t t0 = tile * kScanTile;
   const int n = (int)((P - t0) < kScanTile ? (P - t0) : kScanTile);
-  const T zfirst = key_value<T>(keys, t0);
-  const T zprev = t0 > 0 ? key_value<T>(keys, t0 - 1) : zfirst;
-  const T zlast = key_value<T>(keys, t0 + n - 1);
+  const T zfirst = keys(t0);
+  const T zprev = t0 > 0 ? keys(t0 - 1) : zfirst;
+  const T zlast = keys(t0 + n - 1);
   // Centre c and the exact distances to the tile's outer reference points.
   const T c = zprev + (zlast - zprev) * T(0.5);
   const T hf = zlast - c;
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void*
 #pragma unroll
     for (int m = 0; m <= kMomentMax; ++m) mu[m] = T(0);
     for (int e = lane; e < n; e += kWave) {
-      const T s = key_value<T>(keys, t0 + e) - c;
+      const T s = keys(t0 + e) - c;
       T pw = bs[t0 + e];
       mu[0] += pw;
 #pragma unroll
@@ -140,9 +140,9 @@ __global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void*
     const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
     Seg<T> s = seg_identity<T>();
     // forward map (A, F)
-    T zl = e0 == 0 ? zprev : (cnt > 0 ? key_value<T>(keys, t0 + e0 - 1) : zlast);
+    T zl = e0 == 0 ? zprev : (cnt > 0 ? keys(t0 + e0 - 1) : zlast);
     for (int j = 0; j < cnt; ++j) {
-      const T zj = key_value<T>(keys, t0 + e0 + j);
+      const T zj = keys(t0 + e0 + j);
       const C<T> ex = exp_neg_general<T>(tr, ti, zj - zl);
       s.a = cmul(s.a, ex);
       s.f = cfma(ex, s.f, C<T>{bs[t0 + e0 + j], T(0)});
@@ -151,8 +151,8 @@ __global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void*
     // backward map G, last point first
     C<T> g = {T(0), T(0)};
     for (int j = cnt - 1; j >= 0; --j) {
-      const T zj = key_value<T>(keys, t0 + e0 + j);
-      const T zb = (e0 + j == 0) ? zprev : key_value<T>(keys, t0 + e0 + j - 1);
+      const T zj = keys(t0 + e0 + j);
+      const T zb = (e0 + j == 0) ? zprev : keys(t0 + e0 + j - 1);
       const C<T> ex = exp_neg_general<T>(tr, ti, zj - zb);
       g = cmul(ex, cadd(g, C<T>{bs[t0 + e0 + j], T(0)}));
     }
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const
     const int K = tile_k[blockIdx.x];
     if (K >= 0 && K <= kFastMoments) return;   // handled by k_final_fast
   }
-  const void* keys = pass->final_buf ? keys1 : keys0;
+  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
   __shared__ Staged<T> st;
   __shared__ Seg<T> wtot[NM][kScanWaves][2];   // per wave: [0] forward total, [1] backward total
   const int tid = threadIdx.x;
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const
     for (int r = 0; r < R; ++r) {
       const int64_t p = t0 + tid + r * kScanThreads;
       const bool in = p < P;
-      zr[r] = in ? key_value<T>(keys, p) : T(0);
+      zr[r] = in ? keys(p) : T(0);
       br[r] = in ? bs[p] : T(0);
       sr[r] = in ? ids[p] : kNoSlot;
     }
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const
     }
   }
   T zprev = T(0);
-  if (tid == 0) zprev = t0 > 0 ? key_value<T>(keys, t0 - 1) : T(0);
+  if (tid == 0) zprev = t0 > 0 ? keys(t0 - 1) : T(0);
   __syncthreads();
 
   // This thread's chunk: gaps dz_j = z_j - z_{j-1} and strengths b_j.
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(kScanThreads) void k_final_fast(
   const int64_t tile = blockIdx.x;
   const int K = tile_k[tile];
   if (K < 0 || K > kFastMoments) return;
-  const void* keys = pass->final_buf ? keys1 : keys0;
+  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
   __shared__ FastLds<T> lds;
   __shared__ T mtot[kFastMoments + 1][kScanWaves];
   const int tid = threadIdx.x;
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(kScanThreads) void k_final_fast(
     for (int r = 0; r < R; ++r) {
       const int64_t p = t0 + tid + r * kScanThreads;
       const bool in = p < P;
-      zr[r] = in ? key_value<T>(keys, p) : T(0);
+      zr[r] = in ? keys(p) : T(0);
       br[r] = in ? bs[p] : T(0);
       sr[r] = in ? ids[p] : kNoSlot;
     }
@@ -457,9 +457,9 @@ __global__ __launch_bounds__(kScanThreads) void k_final_fast(
       lds.st.id[q] = sr[r];
     }
   }
-  const T zfirst = key_value<T>(keys, t0);
-  const T zprev = t0 > 0 ? key_value<T>(keys, t0 - 1) : zfirst;
-  const T zlast = key_value<T>(keys, t0 + n - 1);
+  const T zfirst = keys(t0);
+  const T zprev = t0 > 0 ? keys(t0 - 1) : zfirst;
+  const T zlast = keys(t0 + n - 1);
   const T c = zprev + (zlast - zprev) * T(0.5);
   __syncthreads();
 

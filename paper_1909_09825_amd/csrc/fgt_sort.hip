@@ -9,10 +9,12 @@
 //
 // Kernels, all on the caller's stream:
 //   k_clear       zero histograms, tile counters, status word, look-back[0]
-//   k_histogram   one read of the coordinates: all digit histograms at once,
-//                 plus the non-finite flag
-//   k_plan        per pass: does the digit vary?  where does the pass read
-//                 from and write to?  exclusive digit offsets
+//   k_range       (FP64) smallest and largest coordinate, non-finite flag
+//   k_histogram   one read of the coordinates: all digit histograms at once
+//                 (FP32: also the range and the non-finite flag)
+//   k_plan        the FP64 key code for the range; per pass: does the digit
+//                 vary?  where does the pass read from and write to?
+//                 exclusive digit offsets
 //   k_onesweep    one pass per digit: stable in-tile ranking with wave ballots,
 //                 tile offsets by decoupled look-back (Merrill & Garland),
 //                 scatter staged through LDS so writes are coalesced runs.
@@ -43,25 +45,151 @@ __device__ __forceinline__ T load_point(const T* __restrict__ x, const T* __rest
   return p < N ? y[p] : x[p - N];
 }
 
+// Smallest and largest IEEE order key of a thread's points, and whether any
+// is not finite; folded over the block and published with two atomics per
+// block (the smallest as the largest complement, so that zeroed words start
+// both).  publish() is called by every thread of the block.
+struct RangeAcc {
+  uint64_t kmin = ~0ull, kmax = 0ull;
+  bool bad = false;
+  template <class T>
+  __device__ __forceinline__ void add(T z) {
+    const uint64_t k = (uint64_t)to_key(z);
+    kmin = k < kmin ? k : kmin;
+    kmax = k > kmax ? k : kmax;
+    bad |= !isfinite(z);
+  }
+  __device__ __forceinline__ void publish(unsigned long long* range, uint32_t* status) {
+    __shared__ uint64_t wmin[1024 / kWave], wmax[1024 / kWave];
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+      const uint64_t a = __shfl_xor(kmin, o, kWave);
+      const uint64_t b = __shfl_xor(kmax, o, kWave);
+      kmin = a < kmin ? a : kmin;
+      kmax = b > kmax ? b : kmax;
+    }
+    if (bad) atomicOr(status, kStatusNonFinite);
+    const int wave = threadIdx.x / kWave;
+    if ((threadIdx.x % kWave) == 0) {
+      wmin[wave] = kmin;
+      wmax[wave] = kmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < (int)(blockDim.x / kWave); ++w) {
+        kmin = wmin[w] < kmin ? wmin[w] : kmin;
+        kmax = wmax[w] > kmax ? wmax[w] : kmax;
+      }
+      atomicMax(&range[0], (unsigned long long)~kmin);
+      atomicMax(&range[1], (unsigned long long)kmax);
+    }
+  }
+};
+
+template <class T>
+__global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, const T* __restrict__ y,
+                                               int64_t N, int64_t P,
+                                               unsigned long long* __restrict__ range,
+                                               uint32_t* __restrict__ status) {
+  RangeAcc acc;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  constexpr int kBatch = 8;
+  for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p0 < P; p0 += stride * kBatch) {
+    T zb[kBatch];
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      const int64_t p = p0 + i * stride;
+      zb[i] = p < P ? load_point(x, y, N, p) : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i)
+      if (p0 + i * stride < P) acc.add(zb[i]);
+  }
+  acc.publish(range, status);
+}
+
+template <class T>
+__device__ __forceinline__ Codec<T> codec_from_range(const unsigned long long* range,
+                                                     double code_tol) {
+  if constexpr (sizeof(T) == 8) {
+    return make_codec(~(uint64_t)range[0], (uint64_t)range[1], code_tol);
+  } else {
+    (void)range;
+    (void)code_tol;
+    return Codec<float>{};
+  }
+}
+
+// Low digits below the key resolution: keys that agree above digit k differ
+// by less than 256^k, so their coordinates by less than unit (256^k + slack);
+// digits up to the largest such k need not be sorted.
+template <class T>
+__device__ __forceinline__ int digits_below_resolution(const unsigned long long* range,
+                                                       const SortRes& res, const Codec<T>& cd) {
+  constexpr int D = KeyOf<T>::kDigits;
+  double key_width = res.key_width;
+  double unit;   // coordinate distance of one key step (bound)
+  double slack;  // key steps that the encoding may lose
+  if constexpr (sizeof(T) == 8) {
+    if (cd.quant) {
+      // Grid points decode exactly, others move by less than g:
+      // |z1 - z2| < (|q1 - q2| + 1) g.
+      unit = cd.g;
+      slack = 1.0;
+      key_width = res.key_width_q;
+    } else {
+      // IEEE order keys: the largest |z| has the widest spacing, ulp.
+      const double a = from_key((uint64_t)~(uint64_t)range[0]);
+      const double c = from_key((uint64_t)range[1]);
+      const double zmax = fabs(a) > fabs(c) ? fabs(a) : fabs(c);
+      const int ex = (int)((__double_as_longlong(zmax) >> 52) & 0x7ff);
+      unit = ex == 0x7ff ? INFINITY : ldexp(1.0, (ex == 0 ? 1 : ex) - 1075);
+      slack = 0.0;
+    }
+  } else {
+    (void)cd;
+    const float a = from_key((uint32_t)~(uint64_t)range[0]);
+    const float c = from_key((uint32_t)range[1]);
+    const float zmax = fabsf(a) > fabsf(c) ? fabsf(a) : fabsf(c);
+    const int ex = (int)((__float_as_uint(zmax) >> 23) & 0xff);
+    unit = ex == 0xff ? INFINITY : ldexp(1.0, (ex == 0 ? 1 : ex) - 150);
+    slack = 0.0;
+  }
+  int skip = 0;
+  if (key_width > 0.0 && unit < INFINITY) {
+    double keys_per_digit = 1.0;
+    while (skip < D - 1 && unit * (keys_per_digit * 256.0 + slack) <= key_width) {
+      keys_per_digit *= 256.0;
+      ++skip;
+    }
+  }
+  return skip;
+}
+
+// Digit histograms of all keys.  FP64 keys need the range (k_range first),
+// which also tells which low digits the sort skips (not counted); FP32 keys
+// are plain IEEE order keys and the range is gathered here.
 template <class T>
 __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, const T* __restrict__ y,
                                                    int64_t N, int64_t P,
                                                    uint32_t* __restrict__ hist,
                                                    uint32_t* __restrict__ status,
-                                                   unsigned long long* __restrict__ maxabs) {
+                                                   unsigned long long* __restrict__ range,
+                                                   SortRes res) {
   using K = typename KeyOf<T>::type;
   constexpr int D = KeyOf<T>::kDigits;
+  constexpr bool kGatherRange = sizeof(T) == 4;
   __shared__ uint32_t h[D * kRadix];
   for (int i = threadIdx.x; i < D * kRadix; i += blockDim.x) h[i] = 0u;
   __syncthreads();
+  const Codec<T> cd = codec_from_range<T>(range, res.code_tol);
+  const int skip = kGatherRange ? 0 : digits_below_resolution<T>(range, res, cd);
 
   // Run-length counting per digit: constant high digits (common for
   // coordinates of one sign and exponent range) cost one LDS atomic per run.
   uint32_t cur[D], cnt[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) { cur[d] = 0u; cnt[d] = 0u; }
-  bool bad = false;
-  T zmax = T(0);
+  RangeAcc acc;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   constexpr int kBatch = 8;   // loads issued together before they are used
   for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p0 < P; p0 += stride * kBatch) {
@@ -75,11 +203,11 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
     for (int i = 0; i < kBatch; ++i) {
       if (p0 + i * stride >= P) break;
       const T z = zb[i];
-      bad |= !isfinite(z);
-      zmax = fabs(z) > zmax ? fabs(z) : zmax;
-      const K k = to_key(z);
+      if (kGatherRange) acc.add(z);
+      const K k = cd.encode(z);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
+        if (d < skip) continue;
         const uint32_t dig = (uint32_t)(k >> (8 * d)) & 0xffu;
         if (cnt[d] != 0u && dig != cur[d]) {
           atomicAdd(&h[d * kRadix + cur[d]], cnt[d]);
@@ -93,15 +221,7 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
 #pragma unroll
   for (int d = 0; d < D; ++d)
     if (cnt[d]) atomicAdd(&h[d * kRadix + cur[d]], cnt[d]);
-  if (bad) atomicOr(status, kStatusNonFinite);
-  // Non-negative floats order like their bit patterns.
-  unsigned long long zbits = sizeof(T) == 8 ? (unsigned long long)__double_as_longlong((double)zmax)
-                                            : (unsigned long long)__float_as_uint((float)zmax);
-  for (int o = kWave / 2; o >= 1; o >>= 1) {
-    const unsigned long long other = __shfl_xor(zbits, o, kWave);
-    zbits = other > zbits ? other : zbits;
-  }
-  if ((threadIdx.x % kWave) == 0) atomicMax(maxabs, zbits);
+  if (kGatherRange) acc.publish(range, status);
   __syncthreads();
   for (int i = threadIdx.x; i < D * kRadix; i += blockDim.x)
     if (h[i]) atomicAdd(&hist[i], h[i]);
@@ -110,8 +230,8 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
 // One block of 256 threads (one per digit value).
 template <class T>
 __global__ __launch_bounds__(256) void k_plan(const uint32_t* __restrict__ hist, int64_t P,
-                                              const unsigned long long* __restrict__ maxabs,
-                                              double key_width, uint32_t* __restrict__ dig_off,
+                                              const unsigned long long* __restrict__ range,
+                                              SortRes res, uint32_t* __restrict__ dig_off,
                                               PassInfo* __restrict__ pass) {
   constexpr int D = KeyOf<T>::kDigits;
   __shared__ uint32_t scan[kRadix];
@@ -135,28 +255,15 @@ __global__ __launch_bounds__(256) void k_plan(const uint32_t* __restrict__ hist,
     __syncthreads();
   }
   if (b == 0) {
-    // Low digits below the key resolution: the largest |z| has the largest
-    // spacing between neighbouring floats, ulp; keys that agree above digit k
-    // differ by less than 256^k ulp.
-    int skip = 0;
-    {
-      const unsigned long long zb = *maxabs;
-      double ulp;
-      if (sizeof(T) == 8) {
-        const int ex = (int)((zb >> 52) & 0x7ff);
-        ulp = ex == 0x7ff ? INFINITY : ldexp(1.0, (ex == 0 ? 1 : ex) - 1075);
-      } else {
-        const int ex = (int)((zb >> 23) & 0xff);
-        ulp = ex == 0xff ? INFINITY : ldexp(1.0, (ex == 0 ? 1 : ex) - 150);
-      }
-      if (key_width > 0.0 && ulp < INFINITY) {
-        double span = ulp;
-        while (skip < D - 1 && span * 256.0 <= key_width) {
-          span *= 256.0;
-          ++skip;
-        }
-      }
+    const Codec<T> cd = codec_from_range<T>(range, res.code_tol);
+    if constexpr (sizeof(T) == 8) {
+      pass->code_quant = cd.quant;
+      pass->code_F = cd.F;
+      pass->code_L = cd.L;
+      pass->code_g = cd.g;
+      pass->code_inv_g = cd.inv_g;
     }
+    const int skip = digits_below_resolution<T>(range, res, cd);
     for (int d = 0; d < skip; ++d) trivial[d] = 1;
     pass->skipped_low = skip;
     int any = 0;
@@ -228,20 +335,26 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   K key[kSortItems];
   uint32_t id[kSortItems];
   uint32_t rank[kSortItems];
+  // Two separate load loops (the source is the same for the whole pass), each
+  // issuing all of its loads before any is used.
+  if (src == kRaw) {
+    T z[kSortItems];
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    const int64_t p = base + i * kWave + lane;
-    if (p < P) {
-      if (src == kRaw) {
-        key[i] = to_key(load_point(x, y, N, p));
-        id[i] = (uint32_t)p;
-      } else {
-        key[i] = kin[p];
-        id[i] = iin[p];
-      }
-    } else {
-      key[i] = (K)0;
-      id[i] = 0u;
+    for (int i = 0; i < kSortItems; ++i) {
+      const int64_t p = base + i * kWave + lane;
+      z[i] = p < P ? load_point(x, y, N, p) : T(0);
+      id[i] = p < P ? (uint32_t)p : 0u;
+    }
+    const Codec<T> cd = codec_of<T>(pass);
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i)
+      key[i] = base + i * kWave + lane < P ? cd.encode(z[i]) : (K)0;
+  } else {
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+      const int64_t p = base + i * kWave + lane;
+      key[i] = p < P ? kin[p] : (K)0;
+      id[i] = p < P ? iin[p] : 0u;
     }
   }
 
@@ -385,6 +498,10 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   __syncthreads();
   // Each thread visits the same positions j in both write loops; the output
   // index found for the key is kept for the payload.
+  // The last pass stores the sorted coordinates themselves (decoded from the
+  // keys) in place of the keys: the scans read them as they are.
+  const bool last = d == pass->last_pass;
+  const Codec<T> cd = codec_of<T>(pass);
   uint32_t outpos[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
@@ -396,7 +513,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
       const uint64_t out = gbase[dig] + (uint64_t)(j - (int)tstart[dig]);
       if (out < (uint64_t)P) {
         outpos[r] = (uint32_t)out;
-        kout[out] = k;
+        kout[out] = last ? bits_of(cd.decode(k)) : k;
       }
     }
   }
@@ -409,7 +526,6 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   // The last pass writes the final permutation to its own array, which the
   // scans keep using, and the strength of each sorted point (alpha gathered
   // here, once).
-  const bool last = d == pass->last_pass;
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int j = tid + r * kSortThreads;
@@ -425,21 +541,21 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   }
 }
 
-// Points given in ascending order: keys and identity ids as the sort would
-// leave them (the strengths are read in place).
+// Points given in ascending order: the sorted coordinates and identity ids as
+// the sort would leave them (the strengths are read in place).  Unsorted input
+// raises kStatusUnsorted.
 template <class T>
 __global__ __launch_bounds__(256) void k_presorted(const T* __restrict__ x, int64_t N,
-                                                   void* keys0, uint32_t* __restrict__ ids,
+                                                   T* __restrict__ zs, uint32_t* __restrict__ ids,
                                                    PassInfo* __restrict__ pass,
                                                    uint32_t* __restrict__ status) {
-  using K = typename KeyOf<T>::type;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   bool unsorted = false, bad = false;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
     const T z = x[p];
     bad |= !isfinite(z);
-    if (p > 0) unsorted |= z < x[p - 1];
-    ((K*)keys0)[p] = to_key(z);
+    if (p > 0) unsorted |= !(z >= x[p - 1]);
+    zs[p] = z;
     ids[p] = (uint32_t)p;
   }
   if (unsorted) atomicOr(status, kStatusUnsorted);
@@ -460,7 +576,7 @@ hipError_t presorted_points(const Workspace& w, const T* x, const T* alpha, int6
   int64_t blocks = (N + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_presorted<T>, dim3((unsigned)blocks), dim3(256), 0, s, x, N, w.keys[0],
+  hipLaunchKernelGGL(k_presorted<T>, dim3((unsigned)blocks), dim3(256), 0, s, x, N, (T*)w.keys[0],
                      w.ids, w.pass, w.status);
   return hipGetLastError();
 }
@@ -472,7 +588,7 @@ template hipError_t presorted_points<float>(const Workspace&, const float*, cons
 
 template <class T>
 hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, const T* alpha,
-                       int64_t N, double key_width, hipStream_t s, Timeline* tl) {
+                       int64_t N, const SortRes& res, hipStream_t s, Timeline* tl) {
   constexpr int D = KeyOf<T>::kDigits;
   const int64_t P = M + N;
   tl->mark(s);
@@ -482,9 +598,12 @@ hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, co
   int64_t hb = (P + 256 * 16 - 1) / (256 * 16);
   if (hb > kHistBlocks) hb = kHistBlocks;
   if (hb < 1) hb = 1;
+  if (sizeof(T) == 8)
+    hipLaunchKernelGGL(k_range<T>, dim3((unsigned)(hb < 512 ? hb : 512)), dim3(256), 0, s, x, y, N,
+                       P, w.range, w.status);
   hipLaunchKernelGGL(k_histogram<T>, dim3((unsigned)hb), dim3(256), 0, s, x, y, N, P, w.hist,
-                     w.status, w.maxabs);
-  hipLaunchKernelGGL(k_plan<T>, dim3(1), dim3(256), 0, s, w.hist, P, w.maxabs, key_width, w.dig_off,
+                     w.status, w.range, res);
+  hipLaunchKernelGGL(k_plan<T>, dim3(1), dim3(256), 0, s, w.hist, P, w.range, res, w.dig_off,
                      w.pass);
   tl->mark(s);
   for (int d = 0; d < D; ++d) {
@@ -498,8 +617,10 @@ hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, co
 }
 
 template hipError_t sort_points<double>(const Workspace&, const double*, int64_t, const double*,
-                                        const double*, int64_t, double, hipStream_t, Timeline*);
+                                        const double*, int64_t, const SortRes&, hipStream_t,
+                                        Timeline*);
 template hipError_t sort_points<float>(const Workspace&, const float*, int64_t, const float*,
-                                       const float*, int64_t, double, hipStream_t, Timeline*);
+                                       const float*, int64_t, const SortRes&, hipStream_t,
+                                       Timeline*);
 
 }  // namespace fgt

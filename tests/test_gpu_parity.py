@@ -109,6 +109,31 @@ def test_near_duplicates_below_key_resolution(delta):
     full_check(x, y, a, delta, 6, "near-dup")
 
 
+def _code_case(kind, g):
+    if kind == "far_positive":      # range far from 0: offsets from its aligned start
+        y, x = 1e6 + g.random(20000), 1e6 + g.random(15000)
+    elif kind == "far_negative":
+        y, x = -5e3 - 2 * g.random(20000), -5e3 - 2 * g.random(15000)
+    elif kind == "straddle_tiny":   # points below the grid step near 0 move by < g
+        tiny = np.array([1e-20, -1e-20, 3e-310, -3e-310, 0.0, -0.0, 2.0 ** -70])
+        y = np.concatenate([g.uniform(-1, 1, 20000), tiny])
+        x = np.concatenate([g.uniform(-1, 1, 15000), tiny, -tiny])
+    else:                           # "two_points": the smallest non-degenerate range
+        y, x = np.array([0.25, 0.75]), np.array([0.75, 0.25, 0.5])
+    return x, y, g.standard_normal(len(y))
+
+
+@pytest.mark.parametrize("kind", ["far_positive", "far_negative", "straddle_tiny", "two_points"])
+@pytest.mark.parametrize("delta,digits", [(1e-4, 6), (1e-6, 11)])
+def test_fp64_key_code_ranges(kind, delta, digits):
+    """FP64 keys are coded on a grid fitted to the points' range where that
+    moves no point by more than the plan allows (else IEEE keys): ranges far
+    from 0 on either side, ranges through 0 with values below the grid step,
+    tiny sets; 11 digits at delta 1e-6 keeps IEEE keys for ranges through 0."""
+    x, y, a = _code_case(kind, np.random.default_rng(12))
+    full_check(x, y, a, delta, digits, f"code-{kind}")
+
+
 def test_clustered_small():
     pr = W.clustered(log2n=15, log2m=13, delta=1e-5, digits=6, n_comp=16)
     full_check(pr.x, pr.y, pr.alpha, pr.delta, 6, "clustered-small")
