@@ -92,17 +92,21 @@ __global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, const T*
                                                uint32_t* __restrict__ status) {
   RangeAcc acc;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  constexpr int kBatch = 8;
-  for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p0 < P; p0 += stride * kBatch) {
-    T zb[kBatch];
+  constexpr int kBatch = 16;   // loads issued together before they are used
+  for (int part = 0; part < 2; ++part) {
+    const T* __restrict__ a = part == 0 ? y : x;
+    const int64_t n = part == 0 ? N : P - N;
+    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p0 < n;
+         p0 += stride * kBatch) {
+      T zb[kBatch];
 #pragma unroll
-    for (int i = 0; i < kBatch; ++i) {
-      const int64_t p = p0 + i * stride;
-      zb[i] = p < P ? load_point(x, y, N, p) : T(0);
+      for (int i = 0; i < kBatch; ++i) {
+        const int64_t p = p0 + i * stride;
+        zb[i] = p < n ? a[p] : a[p0];
+      }
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) acc.add(zb[i]);
     }
-#pragma unroll
-    for (int i = 0; i < kBatch; ++i)
-      if (p0 + i * stride < P) acc.add(zb[i]);
   }
   acc.publish(range, status);
 }
@@ -227,33 +231,38 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
     if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
-// One block of 256 threads (one per digit value).
+// One block of 8 waves: wave d scans digit d's 256 counts (4 per lane).
 template <class T>
-__global__ __launch_bounds__(256) void k_plan(const uint32_t* __restrict__ hist, int64_t P,
+__global__ __launch_bounds__(512) void k_plan(const uint32_t* __restrict__ hist, int64_t P,
                                               const unsigned long long* __restrict__ range,
                                               SortRes res, uint32_t* __restrict__ dig_off,
                                               PassInfo* __restrict__ pass) {
   constexpr int D = KeyOf<T>::kDigits;
-  __shared__ uint32_t scan[kRadix];
   __shared__ int trivial[8];
   const int b = threadIdx.x;
+  const int wave = b / kWave, lane = b % kWave;
   if (b < 8) trivial[b] = 0;
   __syncthreads();
-  for (int d = 0; d < D; ++d) {
-    const uint32_t c = hist[d * kRadix + b];
-    if ((int64_t)c == P) trivial[d] = 1;
-    scan[b] = c;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over 256 digit counts.
-    for (int o = 1; o < kRadix; o <<= 1) {
-      const uint32_t v = b >= o ? scan[b - o] : 0u;
-      __syncthreads();
-      scan[b] += v;
-      __syncthreads();
+  if (wave < D) {
+    const uint32_t* h = hist + wave * kRadix + 4 * lane;
+    const uint32_t c0 = h[0], c1 = h[1], c2 = h[2], c3 = h[3];
+    if ((int64_t)c0 == P || (int64_t)c1 == P || (int64_t)c2 == P || (int64_t)c3 == P)
+      trivial[wave] = 1;
+    const uint32_t own = c0 + c1 + c2 + c3;
+    uint32_t incl = own;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, (unsigned)o, kWave);
+      if (lane >= o) incl += v;
     }
-    dig_off[d * kRadix + b] = scan[b] - c;
-    __syncthreads();
+    uint32_t* out = dig_off + wave * kRadix + 4 * lane;
+    const uint32_t e0 = incl - own;
+    out[0] = e0;
+    out[1] = e0 + c0;
+    out[2] = e0 + c0 + c1;
+    out[3] = e0 + c0 + c1 + c2;
   }
+  __syncthreads();
   if (b == 0) {
     const Codec<T> cd = codec_from_range<T>(range, res.code_tol);
     if constexpr (sizeof(T) == 8) {
@@ -599,11 +608,11 @@ hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, co
   if (hb > kHistBlocks) hb = kHistBlocks;
   if (hb < 1) hb = 1;
   if (sizeof(T) == 8)
-    hipLaunchKernelGGL(k_range<T>, dim3((unsigned)(hb < 512 ? hb : 512)), dim3(256), 0, s, x, y, N,
-                       P, w.range, w.status);
+    hipLaunchKernelGGL(k_range<T>, dim3((unsigned)(hb < 1024 ? hb : 1024)), dim3(256), 0, s, x, y,
+                       N, P, w.range, w.status);
   hipLaunchKernelGGL(k_histogram<T>, dim3((unsigned)hb), dim3(256), 0, s, x, y, N, P, w.hist,
                      w.status, w.range, res);
-  hipLaunchKernelGGL(k_plan<T>, dim3(1), dim3(256), 0, s, w.hist, P, w.range, res, w.dig_off,
+  hipLaunchKernelGGL(k_plan<T>, dim3(1), dim3(512), 0, s, w.hist, P, w.range, res, w.dig_off,
                      w.pass);
   tl->mark(s);
   for (int d = 0; d < D; ++d) {
