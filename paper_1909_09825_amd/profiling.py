@@ -26,8 +26,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 KERNEL_SOURCES = {
     "k_onesweep": ["paper_1909_09825_amd/csrc/fgt_sort.hip", "paper_1909_09825_amd/csrc/fgt_internal.h"],
-    "k_final_fast": ["paper_1909_09825_amd/csrc/fgt_scan.hip", "paper_1909_09825_amd/csrc/fgt_internal.h"],
-    "k_reduce": ["paper_1909_09825_amd/csrc/fgt_scan.hip", "paper_1909_09825_amd/csrc/fgt_internal.h"],
+    "k_final_fast": ["paper_1909_09825_amd/csrc/fgt_scan.hip", "paper_1909_09825_amd/csrc/fgt_device.h",
+                     "paper_1909_09825_amd/csrc/fgt_internal.h"],
+    "k_reduce": ["paper_1909_09825_amd/csrc/fgt_scan.hip", "paper_1909_09825_amd/csrc/fgt_device.h",
+                 "paper_1909_09825_amd/csrc/fgt_internal.h"],
 }
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
