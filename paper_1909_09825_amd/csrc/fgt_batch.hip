@@ -56,9 +56,11 @@ __device__ __forceinline__ double qscale(double lo, double hi) {
   return isfinite(qs) ? qs : 0.0;
 }
 
-// Key of a coordinate: every kernel evaluates it through this one out-of-line
-// function, so counting and scattering see bit-identical keys.
-__device__ __noinline__ uint64_t quant_key(double z, double scale, double lo, double qs) {
+// Key of a coordinate.  Counting and scattering must see bit-identical keys,
+// so the operations are never contracted into fused multiply-adds (whose
+// rounding could then differ between the kernels it is inlined into).
+__device__ __forceinline__ uint64_t quant_key(double z, double scale, double lo, double qs) {
+#pragma clang fp contract(off)
   const double zp = z * scale;
   double v = (zp - lo) * qs;
   v = v > 0.0 ? v : 0.0;
@@ -104,11 +106,21 @@ __global__ __launch_bounds__(256) void k_seg_minmax(const SegInfo* __restrict__ 
   const int64_t P = sg.M + sg.N;
   double mn = INFINITY, mx = -INFINITY;
   bool bad = false;
-  for (int64_t p = threadIdx.x; p < P; p += 256) {
-    const double z = seg_point(sg, x, y, p) * sg.scale;
-    bad |= !isfinite(z);
-    mn = fmin(mn, z);
-    mx = fmax(mx, z);
+  constexpr int kBatch = 8;   // loads issued together before they are used
+  for (int64_t p0 = threadIdx.x; p0 < P; p0 += 256 * kBatch) {
+    double zb[kBatch];
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      const int64_t p = p0 + i * 256;
+      zb[i] = p < P ? seg_point(sg, x, y, p) : seg_point(sg, x, y, p0);
+    }
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      const double z = zb[i] * sg.scale;
+      bad |= !isfinite(z);
+      mn = fmin(mn, z);
+      mx = fmax(mx, z);
+    }
   }
   for (int o = kWave / 2; o >= 1; o >>= 1) {
     mn = fmin(mn, __shfl_xor(mn, o, kWave));
@@ -149,8 +161,18 @@ __global__ __launch_bounds__(256) void k_seg_count(const SegInfo* __restrict__ s
   const double qs = qscale(l, hi[ch.seg]);
   const int64_t P = sg.M + sg.N;
   const int64_t end = ch.start + kBChunk < P ? ch.start + kBChunk : P;
-  for (int64_t p = ch.start + threadIdx.x; p < end; p += 256)
-    atomicAdd(&hist[bucket_of(point_key(sg, x, y, p, l, qs), sg.nb_log2)], 1u);
+  // All of the thread's loads first, then the keys.
+  constexpr int kPer = kBChunk / 256;
+  double z[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int64_t p = ch.start + threadIdx.x + r * 256;
+    z[r] = p < end ? seg_point(sg, x, y, p) : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r)
+    if (ch.start + threadIdx.x + r * 256 < end)
+      atomicAdd(&hist[bucket_of(quant_key(z[r], sg.scale, l, qs), sg.nb_log2)], 1u);
   __syncthreads();
   const int64_t c = (int64_t)blockIdx.x - sg.chunk0;
   for (int i = threadIdx.x; i < nb; i += 256)
@@ -228,10 +250,16 @@ __global__ __launch_bounds__(256) void k_seg_scatter(const SegInfo* __restrict__
   const int64_t P = sg.M + sg.N;
   const int64_t end = ch.start + kBChunk < P ? ch.start + kBChunk : P;
   uint32_t bk[kRounds], rank[kRounds];
+  double z[kRounds];   // all loads first
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t p = ch.start + (int64_t)wave * (kBChunk / 4) + r * kWave + lane;
+    z[r] = p < end ? seg_point(sg, x, y, p) : 0.0;
+  }
   for (int r = 0; r < kRounds; ++r) {
     const int64_t p = ch.start + (int64_t)wave * (kBChunk / 4) + r * kWave + lane;
     const bool valid = p < end;
-    const uint32_t b = valid ? bucket_of(point_key(sg, x, y, p, l, qs), sg.nb_log2) : 0u;
+    const uint32_t b = valid ? bucket_of(quant_key(z[r], sg.scale, l, qs), sg.nb_log2) : 0u;
     uint64_t peers = __ballot(valid);
     for (int bit = 0; bit < sg.nb_log2; ++bit) {
       const bool on = (b >> bit) & 1u;
@@ -401,13 +429,23 @@ __global__ __launch_bounds__(kBSortThreads) void k_bucket_sort(
     uint64_t key[kBSortItems];
     uint32_t id[kBSortItems];
     bool valid[kBSortItems];
+    // Indices, then the coordinates they point at, then the keys: each group
+    // of loads is issued together.
 #pragma unroll
     for (int i = 0; i < kBSortItems; ++i) {
       const int it = item_index(i);
       valid[i] = it < (int)n;
-      id[i] = valid[i] ? checked(ids_tmp[off + it]) : 0u;
-      key[i] = valid[i] ? point_key(sg, x, y, id[i], l, qs) : 0ull;
+      id[i] = valid[i] ? ids_tmp[off + it] : 0u;
     }
+    double zk[kBSortItems];
+#pragma unroll
+    for (int i = 0; i < kBSortItems; ++i) {
+      if (valid[i]) id[i] = checked(id[i]);
+      zk[i] = valid[i] ? seg_point(sg, x, y, id[i]) : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kBSortItems; ++i)
+      key[i] = valid[i] ? quant_key(zk[i], sg.scale, l, qs) : 0ull;
     const uint64_t first = point_key(sg, x, y, checked(ids_tmp[off]), l, qs);
     uint64_t diff = 0ull;
 #pragma unroll
