@@ -637,23 +637,26 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
 #pragma unroll
   for (int j = 0; j < CH; ++j) acc[j] = 0.0;
 
+  // The tile's scaled gaps (0 at the first point of a transform) and the
+  // wave's largest gap, the same for every mode.
+  constexpr int kPer = (TILE + kBThreads - 1) / kBThreads;
+  double dz[kPer];
+  bool cut[kPer];
+  double dmax = 0.0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int e = tid + q * kBThreads;
+    const uint32_t code = e < TILE ? s_id[e] : kPad;
+    cut[q] = code != kPad && (code & kSegStart);
+    dz[q] = (code == kPad || cut[q]) ? 0.0 : (s_z[e + 1] - s_z[e]) * my_scale;
+    dmax = fmax(dmax, fabs(dz[q]));
+  }
+  for (int o = kWave / 2; o >= 1; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, kWave));
+
 #pragma unroll 1
   for (int k = 0; k < NM; ++k) {
     // Mode exponentials of the tile's gaps, 0 at the first point of a transform.
     {
-      constexpr int kPer = (TILE + kBThreads - 1) / kBThreads;
-      double dz[kPer];
-      bool cut[kPer];
-      double dmax = 0.0;
-#pragma unroll
-      for (int q = 0; q < kPer; ++q) {
-        const int e = tid + q * kBThreads;
-        const uint32_t code = e < TILE ? s_id[e] : kPad;
-        cut[q] = code != kPad && (code & kSegStart);
-        dz[q] = (code == kPad || cut[q]) ? 0.0 : (s_z[e + 1] - s_z[e]) * my_scale;
-        dmax = fmax(dmax, fabs(dz[q]));
-      }
-      for (int o = kWave / 2; o >= 1; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, kWave));
       const double rr = md.tau_abs[k] * dmax;
       int D = kTaylorMax;
 #pragma unroll
@@ -673,11 +676,16 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
           d *= 0.5;
           ++halvings;
         }
-        const int Dq = halvings ? kTaylorMax : D;
+        // One degree for the wave (the full one if any lane halved), so the
+        // coefficients are uniform loads and the polynomial is unrolled.
+        const int Dw = __ballot(halvings != 0) ? kTaylorMax : D;
         C<double> ex = {0.0, 0.0};
-        for (int m = Dq; m >= 0; --m) {
-          ex.re = fma(ex.re, d, md.coef_re[k][m]);
-          ex.im = fma(ex.im, d, md.coef_im[k][m]);
+#pragma unroll
+        for (int m = kTaylorMax; m >= 0; --m) {
+          if (m <= Dw) {
+            ex.re = fma(ex.re, d, md.coef_re[k][m]);
+            ex.im = fma(ex.im, d, md.coef_im[k][m]);
+          }
         }
         for (int h = 0; h < halvings; ++h) ex = cmul(ex, ex);
         if (cut[q]) ex = {0.0, 0.0};
