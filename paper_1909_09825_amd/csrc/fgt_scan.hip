@@ -78,25 +78,40 @@ __global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void*
     T mu[kMomentMax + 1];
 #pragma unroll
     for (int m = 0; m <= kMomentMax; ++m) mu[m] = T(0);
-    for (int e = lane; e < n; e += kWave) {
-      const T s = keys(t0 + e) - c;
-      T pw = bs[t0 + e];
-      mu[0] += pw;
+    // The lane's points in order, kGrp at a time with all their loads issued
+    // before any is used.
+    constexpr int kGrp = 8;
+#pragma unroll 1
+    for (int g0 = 0; g0 < kScanTile / kWave; g0 += kGrp) {
+      T zg[kGrp], bg[kGrp];
 #pragma unroll
-      for (int m = 1; m <= kMomentMax; ++m) {
-        if (m <= K) {
-          pw *= s;
-          mu[m] += pw;
+      for (int i = 0; i < kGrp; ++i) {
+        const int e = lane + (g0 + i) * kWave;
+        const bool in = e < n;
+        zg[i] = in ? keys(t0 + e) : c;
+        bg[i] = in ? bs[t0 + e] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < kGrp; ++i) {
+        const T s = zg[i] - c;
+        T pw = bg[i];
+        mu[0] += pw;
+#pragma unroll
+        for (int m = 1; m <= kMomentMax; ++m) {
+          if (m <= K) {
+            pw *= s;
+            mu[m] += pw;
+          }
         }
       }
     }
-    // Butterfly sums: every lane ends with the same, order-fixed totals.
+    // Butterfly sums: every lane ends with the same, order-fixed totals (the
+    // moments' shuffles interleaved).
 #pragma unroll
-    for (int m = 0; m <= kMomentMax; ++m) {
-      if (m <= K) {
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
 #pragma unroll
-        for (int o = kWave / 2; o >= 1; o >>= 1) mu[m] += shfl_xor(mu[m], o);
-      }
+      for (int m = 0; m <= kMomentMax; ++m)
+        if (m <= K) mu[m] += shfl_xor(mu[m], o);
     }
     if (lane < NM) {
       const int k = lane;
