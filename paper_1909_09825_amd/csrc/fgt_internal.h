@@ -341,10 +341,10 @@ constexpr int kMaxBucketLog2 = 12;
 // Scan: a wave holds 4 chunks x 16 columns, a lane runs consecutive points
 // of one column.
 constexpr int kBCols = 16;
-constexpr int kBThreads = 512;
+constexpr int kBThreads = 256;
 // Points per lane and column: 8 or 16 (chosen per batch by the autotuner);
 // a tile holds (kBThreads / kBCols) chunks.
-constexpr int kBTileMin = (kBThreads / kBCols) * 8;   // 256
+constexpr int kBTileMin = (kBThreads / kBCols) * 8;   // 128
 // Bit of a sorted id that marks the first point of a transform.
 constexpr uint32_t kSegStart = 0x80000000u;
 
