@@ -104,30 +104,33 @@ template <> struct KeyOf<float> { using type = uint32_t; static constexpr int kD
 
 // Order-preserving map from a float to an unsigned key: negative values get
 // all bits flipped, non-negative ones the sign bit set; -0 is mapped to +0 so
-// that equal coordinates get equal keys.
-__device__ __forceinline__ uint64_t to_key(double z) {
-  uint64_t b = (uint64_t)__double_as_longlong(z);
+// that equal coordinates get equal keys.  (Host and device: the key code below
+// is also checked on the CPU.)
+__host__ __device__ __forceinline__ uint64_t to_key(double z) {
+  uint64_t b = __builtin_bit_cast(uint64_t, z);
   if (b == 0x8000000000000000ull) b = 0;
   return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
-__device__ __forceinline__ uint32_t to_key(float z) {
-  uint32_t b = (uint32_t)__float_as_uint(z);
+__host__ __device__ __forceinline__ uint32_t to_key(float z) {
+  uint32_t b = __builtin_bit_cast(uint32_t, z);
   if (b == 0x80000000u) b = 0;
   return (b >> 31) ? ~b : (b | 0x80000000u);
 }
-__device__ __forceinline__ double from_key(uint64_t k) {
-  uint64_t b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
-  return __longlong_as_double((long long)b);
+__host__ __device__ __forceinline__ double from_key(uint64_t k) {
+  const uint64_t b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  return __builtin_bit_cast(double, b);
 }
-__device__ __forceinline__ float from_key(uint32_t k) {
-  uint32_t b = (k >> 31) ? (k & 0x7fffffffu) : ~k;
-  return __uint_as_float(b);
+__host__ __device__ __forceinline__ float from_key(uint32_t k) {
+  const uint32_t b = (k >> 31) ? (k & 0x7fffffffu) : ~k;
+  return __builtin_bit_cast(float, b);
 }
 
-__device__ __forceinline__ uint64_t bits_of(double z) {
-  return (uint64_t)__double_as_longlong(z);
+__host__ __device__ __forceinline__ uint64_t bits_of(double z) {
+  return __builtin_bit_cast(uint64_t, z);
 }
-__device__ __forceinline__ uint32_t bits_of(float z) { return __float_as_uint(z); }
+__host__ __device__ __forceinline__ uint32_t bits_of(float z) {
+  return __builtin_bit_cast(uint32_t, z);
+}
 
 // Sort keys as the radix passes see them.  FP32 coordinates keep their IEEE
 // order keys.  FP64 coordinates are, where that loses nothing that matters,
@@ -145,7 +148,7 @@ template <> struct Codec<double> {
   int64_t F;       // grid index of the range's aligned start when L = 0
   int32_t quant;   // 0: IEEE order keys
   static constexpr int64_t kMax = int64_t(1) << 61;
-  __device__ __forceinline__ uint64_t encode(double z) const {
+  __host__ __device__ __forceinline__ uint64_t encode(double z) const {
     if (!quant) return to_key(z);
     double t = (z - L) * inv_g;                 // exact for grid points
     const double t0 = (double)F;                // exact (a multiple of 2^60)
@@ -153,14 +156,14 @@ template <> struct Codec<double> {
     t = t < t0 + (double)kMax ? t : t0 + (double)kMax;
     return (uint64_t)((int64_t)t - F);
   }
-  __device__ __forceinline__ double decode(uint64_t q) const {
+  __host__ __device__ __forceinline__ double decode(uint64_t q) const {
     if (!quant) return from_key(q);
     return fma((double)((int64_t)q + F), g, L);
   }
 };
 template <> struct Codec<float> {
-  __device__ __forceinline__ uint32_t encode(float z) const { return to_key(z); }
-  __device__ __forceinline__ float decode(uint32_t k) const { return from_key(k); }
+  __host__ __device__ __forceinline__ uint32_t encode(float z) const { return to_key(z); }
+  __host__ __device__ __forceinline__ float decode(uint32_t k) const { return from_key(k); }
 };
 
 // Code for points whose smallest and largest IEEE order keys are kmin, kmax.
@@ -171,8 +174,8 @@ template <> struct Codec<float> {
 // scaling, |z / g| < 5 2^60) less lo_a / g; points with |z| < 2^(E-8) may lie off
 // the grid and move by less than g, which must not exceed code_tol.
 // Degenerate ranges (non-finite, all equal, extreme exponents) keep IEEE keys.
-__device__ __forceinline__ Codec<double> make_codec(uint64_t kmin, uint64_t kmax,
-                                                    double code_tol) {
+__host__ __device__ __forceinline__ Codec<double> make_codec(uint64_t kmin, uint64_t kmax,
+                                                             double code_tol) {
   Codec<double> c{0.0, 0.0, 0.0, 0, 0};
   const double lo = from_key(kmin), hi = from_key(kmax);
   if (!(isfinite(lo) && isfinite(hi) && hi > lo)) return c;
