@@ -52,7 +52,7 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   // The region cleared at the start of each call is contiguous: status word
   // (always at offset 0), histograms, tile counters and the first look-back buffer.
   w.status = (uint32_t*)take(sizeof(uint32_t) * 64);
-  w.range = (unsigned long long*)take(2 * sizeof(unsigned long long));
+  w.range = (unsigned long long*)take(3 * sizeof(unsigned long long));
   w.hist = (uint32_t*)take(sizeof(uint32_t) * digits * kRadix);
   w.tile_ctr = (uint32_t*)take(sizeof(uint32_t) * 8);
   w.lookback[0] = (uint64_t*)take(sizeof(uint64_t) * (size_t)w.sort_tiles * kRadix);

@@ -134,31 +134,31 @@ __host__ __device__ __forceinline__ uint32_t bits_of(float z) {
 
 // Sort keys as the radix passes see them.  FP32 coordinates keep their IEEE
 // order keys.  FP64 coordinates are, where that loses nothing that matters,
-// coded as fixed-point offsets on a power-of-two grid g sized to the range
-// [lo, hi] of the call's points (hi - lo < 2^61 g): the key bits are spent on
+// coded as fixed-point offsets on a power-of-two grid g fitted to the range
+// [lo, hi] of the call's points (keys below 2^63): the key bits are spent on
 // the occupied interval, and more low digits fall below the sort resolution
-// and are skipped.  Coordinates on the grid (every |z| >= 2^-8 of the range's
-// power of two, or all of them when the range sits far from 0) decode
-// exactly; smaller ones are truncated by less than g, and the code is used
-// only when such a shift is within the plan's tolerance (else IEEE keys).
+// and are skipped.  Coordinates on the grid (those with ulp(z) >= g, or all of
+// them when the range sits far from 0) decode exactly; smaller ones are
+// truncated by less than g, and the code is used only when such a shift is
+// within the plan's tolerance (else IEEE keys).
 template <class T> struct Codec;
 template <> struct Codec<double> {
   double L;        // offset subtracted before scaling (exact by Sterbenz), or 0
   double g, inv_g; // grid step 2^e and its inverse
   int64_t F;       // grid index of the range's aligned start when L = 0
   int32_t quant;   // 0: IEEE order keys
-  static constexpr int64_t kMax = int64_t(1) << 61;
   __host__ __device__ __forceinline__ uint64_t encode(double z) const {
     if (!quant) return to_key(z);
-    double t = (z - L) * inv_g;                 // exact for grid points
-    const double t0 = (double)F;                // exact (a multiple of 2^60)
+    double t = (z - L) * inv_g;                 // exact for grid points, below 2^63
+    const double t0 = (double)F;                // exact
+    const double top = 9223372036854773760.0;   // 2^63 - 2048: the int64 conversion stays defined
     t = t > t0 ? t : t0;                        // (NaN lands here too)
-    t = t < t0 + (double)kMax ? t : t0 + (double)kMax;
-    return (uint64_t)((int64_t)t - F);
+    t = t < top ? t : top;
+    return (uint64_t)(int64_t)t - (uint64_t)F;
   }
   __host__ __device__ __forceinline__ double decode(uint64_t q) const {
     if (!quant) return from_key(q);
-    return fma((double)((int64_t)q + F), g, L);
+    return fma((double)(int64_t)(q + (uint64_t)F), g, L);
   }
 };
 template <> struct Codec<float> {
@@ -166,16 +166,32 @@ template <> struct Codec<float> {
   __host__ __device__ __forceinline__ float decode(uint32_t k) const { return from_key(k); }
 };
 
+// Exponent of the largest power of two that divides z (finite, non-zero): the
+// value of its lowest set significand bit.  Branch-free: a normal number's
+// implicit bit is bit 52 and its scale 2^(e-1075); a subnormal's scale is
+// 2^-1074 and its significand is below 2^52, so setting bit 52 changes no
+// trailing zero count that matters.
+__host__ __device__ __forceinline__ int granularity_exp(double z) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, z) & 0x7fffffffffffffffull;
+  const int e = (int)(b >> 52);
+  return (e > 1 ? e : 1) - 1075 + (int)__builtin_ctzll(b | (1ull << 52));
+}
+
 // Code for points whose smallest and largest IEEE order keys are kmin, kmax.
-// With span = hi - lo < 2^E the grid is g = 2^(E-60) and the range starts at
-// lo_a = floor(lo / 2^E) 2^E, so every key is below 2^61.  If |lo_a| >= 2^(E+2)
-// all points share lo_a's sign and lie within a factor 2 of it: z - lo_a is
-// exact and a multiple of g.  Otherwise keys are z / g (exact power-of-two
-// scaling, |z / g| < 5 2^60) less lo_a / g; points with |z| < 2^(E-8) may lie off
-// the grid and move by less than g, which must not exceed code_tol.
-// Degenerate ranges (non-finite, all equal, extreme exponents) keep IEEE keys.
+// With span = hi - lo < 2^E the range starts at lo_a = floor(lo / 2^E) 2^E, so
+// every point lies in [lo_a, lo_a + 2^(E+1)).  If |lo_a| >= 2^(E+2) all points
+// share lo_a's sign and lie within a factor 2 of it: z - lo_a is exact and a
+// multiple of g = 2^(E-62), and the keys (z - lo_a) / g are below 2^63.
+// Otherwise the keys are z / g - lo_a / g (exact power-of-two scaling) with g
+// the smallest power of two that keeps |z| / g and the keys below 2^63.  A
+// point is on that grid when it is a multiple of g; `gran` is the exponent of
+// the largest power of two that every point is a multiple of (see
+// granularity_exp; very large when unknown points are all zero).  If some
+// point is finer than g it moves by less than g, which must not exceed
+// code_tol.  Degenerate ranges (non-finite, all equal, extreme exponents) keep
+// IEEE keys.
 __host__ __device__ __forceinline__ Codec<double> make_codec(uint64_t kmin, uint64_t kmax,
-                                                             double code_tol) {
+                                                             int gran, double code_tol) {
   Codec<double> c{0.0, 0.0, 0.0, 0, 0};
   const double lo = from_key(kmin), hi = from_key(kmax);
   if (!(isfinite(lo) && isfinite(hi) && hi > lo)) return c;
@@ -187,18 +203,21 @@ __host__ __device__ __forceinline__ Codec<double> make_codec(uint64_t kmin, uint
   const double pE = ldexp(1.0, E);
   double lo_a = floor(lo / pE) * pE;
   if (lo_a > lo) lo_a -= pE;
-  const double g = ldexp(1.0, E - 60);
+  int eg = E - 62;
   if (fabs(lo_a) >= 4.0 * pE) {
     c.L = lo_a;
     c.F = 0;
   } else {
-    const double small = ldexp(1.0, E - 8);
-    if (lo < small && hi > -small && !(g <= code_tol)) return c;
+    const double m = fabs(lo_a) > fabs(hi) ? fabs(lo_a) : fabs(hi);
+    int em = 0;
+    (void)frexp(m, &em);                        // |z| <= m < 2^em
+    if (em - 63 > eg) eg = em - 63;
+    if (gran < eg && !(ldexp(1.0, eg) <= code_tol)) return c;
     c.L = 0.0;
-    c.F = (int64_t)(lo_a * ldexp(1.0, 60 - E));
+    c.F = (int64_t)(lo_a * ldexp(1.0, -eg));
   }
-  c.g = g;
-  c.inv_g = ldexp(1.0, 60 - E);
+  c.g = ldexp(1.0, eg);
+  c.inv_g = ldexp(1.0, -eg);
   c.quant = 1;
   return c;
 }
@@ -259,7 +278,8 @@ struct Workspace {
                          //     sources); shares the permutation buffers, which are dead after the sort
   double* tile_part;     // [scan_tiles] per-tile parts of the delta-gradient sum
   uint32_t* status;      // [1] at offset 0, zeroed per call
-  unsigned long long* range;   // [2] ~(smallest key), largest key (IEEE order), zeroed per call
+  unsigned long long* range;   // [3] ~(smallest key), largest key (IEEE order), and (FP64)
+                               // 2048 - the finest granularity exponent of the points; zeroed per call
   uint32_t* hist;        // [digits][256], zeroed per call
   uint32_t* tile_ctr;    // [8], zeroed per call
   uint64_t* lookback[2]; // [sort_tiles][256]; [0] zeroed per call, each pass clears the other

@@ -51,6 +51,7 @@ __device__ __forceinline__ T load_point(const T* __restrict__ x, const T* __rest
 // both).  publish() is called by every thread of the block.
 struct RangeAcc {
   uint64_t kmin = ~0ull, kmax = 0ull;
+  uint32_t gran = 0u;   // 2048 - the finest granularity exponent seen (FP64), 0 if none
   bool bad = false;
   template <class T>
   __device__ __forceinline__ void add(T z) {
@@ -58,35 +59,45 @@ struct RangeAcc {
     kmin = k < kmin ? k : kmin;
     kmax = k > kmax ? k : kmax;
     bad |= !isfinite(z);
+    if constexpr (sizeof(T) == 8) {
+      const uint32_t gv = (z != 0.0 && isfinite(z)) ? (uint32_t)(2048 - granularity_exp(z)) : 0u;
+      gran = gv > gran ? gv : gran;
+    }
   }
   __device__ __forceinline__ void publish(unsigned long long* range, uint32_t* status) {
     __shared__ uint64_t wmin[1024 / kWave], wmax[1024 / kWave];
+    __shared__ uint32_t wgran[1024 / kWave];
     for (int o = kWave / 2; o >= 1; o >>= 1) {
       const uint64_t a = __shfl_xor(kmin, o, kWave);
       const uint64_t b = __shfl_xor(kmax, o, kWave);
+      const uint32_t c = __shfl_xor(gran, o, kWave);
       kmin = a < kmin ? a : kmin;
       kmax = b > kmax ? b : kmax;
+      gran = c > gran ? c : gran;
     }
     if (bad) atomicOr(status, kStatusNonFinite);
     const int wave = threadIdx.x / kWave;
     if ((threadIdx.x % kWave) == 0) {
       wmin[wave] = kmin;
       wmax[wave] = kmax;
+      wgran[wave] = gran;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       for (int w = 1; w < (int)(blockDim.x / kWave); ++w) {
         kmin = wmin[w] < kmin ? wmin[w] : kmin;
         kmax = wmax[w] > kmax ? wmax[w] : kmax;
+        gran = wgran[w] > gran ? wgran[w] : gran;
       }
       atomicMax(&range[0], (unsigned long long)~kmin);
       atomicMax(&range[1], (unsigned long long)kmax);
+      if (gran) atomicMax(&range[2], (unsigned long long)gran);
     }
   }
 };
 
 template <class T>
-__global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, const T* __restrict__ y,
+__global__ __launch_bounds__(1024) void k_range(const T* __restrict__ x, const T* __restrict__ y,
                                                int64_t N, int64_t P,
                                                unsigned long long* __restrict__ range,
                                                uint32_t* __restrict__ status) {
@@ -115,7 +126,8 @@ template <class T>
 __device__ __forceinline__ Codec<T> codec_from_range(const unsigned long long* range,
                                                      double code_tol) {
   if constexpr (sizeof(T) == 8) {
-    return make_codec(~(uint64_t)range[0], (uint64_t)range[1], code_tol);
+    const int gran = range[2] ? 2048 - (int)range[2] : 1 << 20;
+    return make_codec(~(uint64_t)range[0], (uint64_t)range[1], gran, code_tol);
   } else {
     (void)range;
     (void)code_tol;
@@ -608,7 +620,8 @@ hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, co
   if (hb > kHistBlocks) hb = kHistBlocks;
   if (hb < 1) hb = 1;
   if (sizeof(T) == 8)
-    hipLaunchKernelGGL(k_range<T>, dim3((unsigned)(hb < 1024 ? hb : 1024)), dim3(256), 0, s, x, y,
+    // Few large blocks: each block ends with atomics on the same three words.
+    hipLaunchKernelGGL(k_range<T>, dim3((unsigned)(hb < 256 ? hb : 256)), dim3(1024), 0, s, x, y,
                        N, P, w.range, w.status);
   hipLaunchKernelGGL(k_histogram<T>, dim3((unsigned)hb), dim3(256), 0, s, x, y, N, P, w.hist,
                      w.status, w.range, res);

@@ -2,12 +2,13 @@
 // make_codec in csrc/fgt_internal.h), compiled for the host only.
 //
 // For point sets of many kinds of range it checks what the sort and the scans
-// rely on: keys of the grid code stay below 2^61; the key order never
+// rely on: keys of the grid code stay below 2^63; the key order never
 // contradicts the coordinate order; coordinates on the grid decode exactly and
 // the others move by less than the grid step g; neighbours differ by less than
-// (key difference + 1) g, the bound the sort's resolution rule uses; the IEEE
-// order keys are taken where the range is degenerate or the grid step exceeds
-// the tolerance, and they decode exactly.  Prints one line per case (and one
+// (key difference + 1) g, the bound the sort's resolution rule uses; the grid
+// code is taken without any tolerance when every point lies on the grid (the
+// data's granularity), and IEEE order keys where the range is degenerate or an
+// off-grid shift would exceed the tolerance, and they decode exactly.  Prints one line per case (and one
 // per failed check) and exits non-zero if any check failed.
 #include <math.h>
 #include <stdio.h>
@@ -19,6 +20,7 @@
 
 using fgt::Codec;
 using fgt::from_key;
+using fgt::granularity_exp;
 using fgt::make_codec;
 using fgt::to_key;
 
@@ -45,16 +47,18 @@ void fail(const char* name, const char* what, double z) {
 // expect: 1 grid code, 0 IEEE keys, -1 either.
 void check(const char* name, const std::vector<double>& z, double tol, int expect) {
   uint64_t kmin = ~0ull, kmax = 0ull;
+  int gran = 1 << 20;
   for (double v : z) {
     kmin = std::min(kmin, to_key(v));
     kmax = std::max(kmax, to_key(v));
+    if (v != 0.0 && isfinite(v)) gran = std::min(gran, granularity_exp(v));
   }
-  const Codec<double> c = make_codec(kmin, kmax, tol);
+  const Codec<double> c = make_codec(kmin, kmax, gran, tol);
   if (expect >= 0 && c.quant != expect) {
     fail(name, expect ? "expected the grid code" : "expected IEEE keys", 0.0);
     return;
   }
-  const double small = c.quant ? ldexp(c.g, 52) : 0.0;   // 2^(E-8): below it a point may be off the grid
+  const double small = c.quant ? ldexp(c.g, 52) : 0.0;   // below it a point may be off the grid
   std::vector<uint64_t> q(z.size());
   double max_off = 0.0;
   for (size_t i = 0; i < z.size(); ++i) {
@@ -64,13 +68,14 @@ void check(const char* name, const std::vector<double>& z, double tol, int expec
       if (!(d == z[i]) && !(isnan(d) && isnan(z[i]))) fail(name, "IEEE key does not decode exactly", z[i]);
       continue;
     }
-    if (q[i] > (uint64_t(1) << 61)) fail(name, "key above 2^61", z[i]);
+    if (q[i] >= (uint64_t(1) << 63)) fail(name, "key not below 2^63", z[i]);
     if (c.L != 0.0 || fabs(z[i]) >= small) {
       if (d != z[i]) fail(name, "grid point does not decode exactly", z[i]);
     } else {
       const double off = fabs(d - z[i]);
       max_off = std::max(max_off, off);
       if (!(off < c.g)) fail(name, "off-grid point moved by g or more", z[i]);
+      if (off > tol) fail(name, "point moved by more than the tolerance", z[i]);
     }
   }
   bool any_nan = false;
@@ -106,6 +111,12 @@ int main() {
   z.clear();
   for (int i = 0; i < n; ++i) z.push_back(r.uni());
   check("uniform [0,1)", z, 1e-15, 1);
+  check("uniform [0,1), no tolerance", z, 0.0, 1);   // multiples of 2^-53: all on the grid
+
+  z.clear();
+  for (int i = 0; i < n; ++i) z.push_back(r.uni() / 3.0);
+  check("[0,1/3), full significands", z, 1e-15, 1);
+  check("[0,1/3), tight tol", z, 1e-30, 0);
 
   z.clear();
   for (int i = 0; i < n; ++i) z.push_back(r.uni());
@@ -124,7 +135,9 @@ int main() {
   z.clear();
   for (int i = 0; i < n; ++i) z.push_back(-1e6 + 2e6 * r.uni());
   check("[-1e6, 1e6), loose tol", z, 1e-9, 1);
-  check("[-1e6, 1e6), tight tol", z, 1e-20, 0);
+  check("[-1e6, 1e6), all on grid", z, 0.0, 1);
+  z.push_back(1e-300);
+  check("[-1e6, 1e6) + 1e-300", z, 1e-20, 0);
 
   z.clear();
   for (int i = 0; i < n; ++i) z.push_back(5.0 + 2.0 * r.uni());

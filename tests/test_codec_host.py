@@ -4,7 +4,7 @@
 as host code over many kinds of range: ranges away from 0 (offset grid),
 through 0 with values below the grid step, [0,1) data as in the benchmark,
 huge, subnormal, overflowing and non-finite ranges.  It checks that grid keys
-stay below 2^61, that key order never contradicts coordinate order, that grid
+stay below 2^63, that key order never contradicts coordinate order, that grid
 points decode exactly and others move by less than the grid step g, the
 (key difference + 1) g gap bound the sort's resolution rule relies on, and
 that IEEE keys are used (and decode exactly) where the grid step would exceed
