@@ -225,10 +225,10 @@ __host__ __device__ __forceinline__ Codec<double> make_codec(uint64_t kmin, uint
 struct PassInfo {
   int32_t run[8];     // 1 if radix pass d moves data
   int32_t src[8];     // 0/1: key buffer it reads, 2: the raw coordinates
-  int32_t final_buf;  // buffer that holds the sorted keys at the end
-  int32_t last_pass;  // the last pass that runs; it also writes strengths and the final ids
+  int32_t final_buf;  // buffer that holds the sorted coordinates at the end
+  int32_t last_pass;  // the last pass that runs; it also writes coordinates, strengths and ids
   int32_t skipped_low;  // low digits left unsorted (below the plan's key resolution)
-  int32_t code_quant;   // FP64 key code of the sorted keys (Codec<double>)
+  int32_t code_quant;   // FP64 key code of this sort's keys (Codec<double>)
   int64_t code_F;
   double code_L, code_g, code_inv_g;
 };
@@ -324,7 +324,7 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes);
 template <class T>
 hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, const T* alpha,
                        int64_t N, const SortRes& res, hipStream_t s, Timeline* tl);
-// Scan of strengths `b` ([P], sorted order) over the sorted keys; writes what
+// Scan of strengths `b` ([P], sorted order) over the sorted coordinates; writes what
 // `out` asks for.
 template <class T>
 hipError_t scan_points(const Workspace& w, const Modes& m, int64_t P, const T* b,
@@ -340,7 +340,7 @@ hipError_t adjoint_points(const Workspace& w, const Modes& md, int64_t M, int64_
                           T* dx, T* dalpha, T* dy, T* ddelta, double delta, hipStream_t s);
 template <class T>
 hipError_t fill_zero(T* u, int64_t n, hipStream_t s);
-// Points given in ascending order: keys and identity ids written as the sort
+// Points given in ascending order: coordinates and identity ids written as the sort
 // would leave them (the scan then reads alpha in place); order and finiteness
 // checked.
 template <class T>

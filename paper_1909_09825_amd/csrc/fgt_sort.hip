@@ -2,23 +2,28 @@
 //
 // The paper sorts targets and sources in ascending order before the
 // recurrences (Section 4) and times that step separately (Tables 1-2).  Here
-// both sets are sorted together as order-preserving unsigned keys with a
-// 32-bit payload p (p < N: source p, else target p - N).  Stability places a
-// source before a target with the same coordinate, which realises the
-// "y_j <= x_i belongs to h+" split of (4.4).
+// both sets are sorted together as order-preserving unsigned keys (FP64: the
+// grid code of Codec<double>, else IEEE order keys) with a 32-bit payload p
+// (p < N: source p, else target p - N).  Stability places a source before a
+// target with the same coordinate, which realises the "y_j <= x_i belongs to
+// h+" split of (4.4).
 //
 // Kernels, all on the caller's stream:
 //   k_clear       zero histograms, tile counters, status word, look-back[0]
-//   k_range       (FP64) smallest and largest coordinate, non-finite flag
-//   k_histogram   one read of the coordinates: all digit histograms at once
-//                 (FP32: also the range and the non-finite flag)
+//   k_range       (FP64) smallest and largest coordinate, their finest
+//                 power-of-two granularity, non-finite flag
+//   k_histogram   one read of the coordinates: the histograms of all digits
+//                 above the sort resolution at once (FP32: all digits, and the
+//                 range and the non-finite flag)
 //   k_plan        the FP64 key code for the range; per pass: does the digit
 //                 vary?  where does the pass read from and write to?
 //                 exclusive digit offsets
 //   k_onesweep    one pass per digit: stable in-tile ranking with wave ballots,
 //                 tile offsets by decoupled look-back (Merrill & Garland),
 //                 scatter staged through LDS so writes are coalesced runs.
-//                 Passes whose digit is constant return at once.
+//                 Passes whose digit is constant return at once.  The last
+//                 pass stores the decoded coordinates, the final ids and the
+//                 strengths (alpha gathered once).
 #include "fgt_internal.h"
 
 namespace fgt {
