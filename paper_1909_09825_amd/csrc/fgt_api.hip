@@ -53,12 +53,12 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   // (always at offset 0), histograms, tile counters and the first look-back buffer.
   w.status = (uint32_t*)take(sizeof(uint32_t) * 64);
   w.range = (unsigned long long*)take(3 * sizeof(unsigned long long));
-  w.hist = (uint32_t*)take(sizeof(uint32_t) * digits * kRadix);
+  w.hist = (uint32_t*)take(sizeof(uint32_t) * digits * kSortRadix);
   w.tile_ctr = (uint32_t*)take(sizeof(uint32_t) * 8);
-  w.lookback[0] = (uint64_t*)take(sizeof(uint64_t) * (size_t)w.sort_tiles * kRadix);
+  w.lookback[0] = (uint64_t*)take(sizeof(uint64_t) * (size_t)w.sort_tiles * kSortRadix);
   w.zero_bytes = off;
-  w.lookback[1] = (uint64_t*)take(sizeof(uint64_t) * (size_t)w.sort_tiles * kRadix);
-  w.dig_off = (uint32_t*)take(sizeof(uint32_t) * digits * kRadix);
+  w.lookback[1] = (uint64_t*)take(sizeof(uint64_t) * (size_t)w.sort_tiles * kSortRadix);
+  w.dig_off = (uint32_t*)take(sizeof(uint32_t) * digits * kSortRadix);
   w.pass = (PassInfo*)take(sizeof(PassInfo));
   // Scan state for up to 2 x n_modes scans (the adjoint runs two strength channels).
   const size_t nq = 2 * (size_t)n_modes;

@@ -83,6 +83,10 @@ constexpr int kSortWaves = kSortThreads / kWave;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 8192 keys per tile
 constexpr int kRadix = 256;
+// Digits of the single-transform sort: 8 or 9 bits, chosen per call on the
+// device (the batched bucket sort keeps 8-bit digits); tables are sized for 9.
+constexpr int kSortBits = 9;
+constexpr int kSortRadix = 1 << kSortBits;
 constexpr int kHistBlocks = 2048;
 
 // Scan: each thread owns a run of kScanChunk consecutive sorted points.
@@ -227,7 +231,9 @@ struct PassInfo {
   int32_t src[8];     // 0/1: key buffer it reads, 2: the raw coordinates
   int32_t final_buf;  // buffer that holds the sorted coordinates at the end
   int32_t last_pass;  // the last pass that runs; it also writes coordinates, strengths and ids
-  int32_t skipped_low;  // low digits left unsorted (below the plan's key resolution)
+  int32_t skipped_low;  // low key bits left unsorted (below the plan's key resolution)
+  int32_t shift[8];     // lowest bit of pass d's digit
+  int32_t bits;         // digit width of this sort, 8 or 9
   int32_t code_quant;   // FP64 key code of this sort's keys (Codec<double>)
   int64_t code_F;
   double code_L, code_g, code_inv_g;

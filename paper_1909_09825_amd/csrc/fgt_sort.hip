@@ -140,13 +140,13 @@ __device__ __forceinline__ Codec<T> codec_from_range(const unsigned long long* r
   }
 }
 
-// Low digits below the key resolution: keys that agree above digit k differ
-// by less than 256^k, so their coordinates by less than unit (256^k + slack);
-// digits up to the largest such k need not be sorted.
+// Sort resolution in key bits.  Keys that agree above bit b differ by less
+// than 2^b, so their coordinates by less than unit (2^b + slack): the lowest
+// b bits with unit (2^b + slack) <= the resolution need not be sorted.  *top:
+// the keys are below 2^top.
 template <class T>
-__device__ __forceinline__ int digits_below_resolution(const unsigned long long* range,
-                                                       const SortRes& res, const Codec<T>& cd) {
-  constexpr int D = KeyOf<T>::kDigits;
+__device__ __forceinline__ int resolution_bits(const unsigned long long* range,
+                                               const SortRes& res, const Codec<T>& cd, int* top) {
   double key_width = res.key_width;
   double unit;   // coordinate distance of one key step (bound)
   double slack;  // key steps that the encoding may lose
@@ -157,6 +157,7 @@ __device__ __forceinline__ int digits_below_resolution(const unsigned long long*
       unit = cd.g;
       slack = 1.0;
       key_width = res.key_width_q;
+      *top = 63;
     } else {
       // IEEE order keys: the largest |z| has the widest spacing, ulp.
       const double a = from_key((uint64_t)~(uint64_t)range[0]);
@@ -165,6 +166,7 @@ __device__ __forceinline__ int digits_below_resolution(const unsigned long long*
       const int ex = (int)((__double_as_longlong(zmax) >> 52) & 0x7ff);
       unit = ex == 0x7ff ? INFINITY : ldexp(1.0, (ex == 0 ? 1 : ex) - 1075);
       slack = 0.0;
+      *top = 64;
     }
   } else {
     (void)cd;
@@ -174,21 +176,46 @@ __device__ __forceinline__ int digits_below_resolution(const unsigned long long*
     const int ex = (int)((__float_as_uint(zmax) >> 23) & 0xff);
     unit = ex == 0xff ? INFINITY : ldexp(1.0, (ex == 0 ? 1 : ex) - 150);
     slack = 0.0;
+    *top = 32;
   }
-  int skip = 0;
-  if (key_width > 0.0 && unit < INFINITY) {
-    double keys_per_digit = 1.0;
-    while (skip < D - 1 && unit * (keys_per_digit * 256.0 + slack) <= key_width) {
-      keys_per_digit *= 256.0;
-      ++skip;
-    }
-  }
-  return skip;
+  int lo = 0;
+  if (key_width > 0.0 && unit < INFINITY)
+    while (lo < *top - 1 && unit * (ldexp(1.0, lo + 1) + slack) <= key_width) ++lo;
+  return lo;
 }
 
-// Digit histograms of all keys.  FP64 keys need the range (k_range first),
-// which also tells which low digits the sort skips (not counted); FP32 keys
-// are plain IEEE order keys and the range is gathered here.
+// Digits of this sort.  FP64: the bits from the resolution to the top of the
+// keys are cut into passes of 8 or 9 bits, whichever needs fewer passes (8 on
+// a tie).  FP32 (whose histograms are counted while its range is still being
+// gathered): four 8-bit digits from bit 0, of which k_plan skips the ones
+// below the resolution.
+struct DigitLayout {
+  int lo_bit;   // lowest sorted bit
+  int bits;     // digit width, 8 or 9
+  int passes;   // 1 .. 8
+};
+template <class T>
+__device__ __forceinline__ DigitLayout digit_layout(const unsigned long long* range,
+                                                    const SortRes& res, const Codec<T>& cd) {
+  DigitLayout L{0, 8, 4};
+  if constexpr (sizeof(T) == 8) {
+    int top = 64;
+    L.lo_bit = resolution_bits<T>(range, res, cd, &top);
+    const int nb = top - L.lo_bit;
+    const int p8 = (nb + 7) / 8, p9 = (nb + 8) / 9;
+    L.bits = p9 < p8 ? 9 : 8;
+    L.passes = p9 < p8 ? p9 : p8;
+  } else {
+    (void)range;
+    (void)res;
+    (void)cd;
+  }
+  return L;
+}
+
+// Histograms of every pass's digit of all keys.  FP64 keys need the range
+// (k_range first), which also fixes the digit layout; FP32 keys are plain IEEE
+// order keys and the range is gathered here.
 template <class T>
 __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, const T* __restrict__ y,
                                                    int64_t N, int64_t P,
@@ -199,11 +226,12 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
   using K = typename KeyOf<T>::type;
   constexpr int D = KeyOf<T>::kDigits;
   constexpr bool kGatherRange = sizeof(T) == 4;
-  __shared__ uint32_t h[D * kRadix];
-  for (int i = threadIdx.x; i < D * kRadix; i += blockDim.x) h[i] = 0u;
+  __shared__ uint32_t h[D * kSortRadix];
+  for (int i = threadIdx.x; i < D * kSortRadix; i += blockDim.x) h[i] = 0u;
   __syncthreads();
   const Codec<T> cd = codec_from_range<T>(range, res.code_tol);
-  const int skip = kGatherRange ? 0 : digits_below_resolution<T>(range, res, cd);
+  const DigitLayout L = digit_layout<T>(range, res, cd);
+  const uint32_t mask = (1u << L.bits) - 1u;
 
   // Run-length counting per digit: constant high digits (common for
   // coordinates of one sign and exponent range) cost one LDS atomic per run.
@@ -228,10 +256,10 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
       const K k = cd.encode(z);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        if (d < skip) continue;
-        const uint32_t dig = (uint32_t)(k >> (8 * d)) & 0xffu;
+        if (d >= L.passes) continue;
+        const uint32_t dig = (uint32_t)(k >> (L.lo_bit + L.bits * d)) & mask;
         if (cnt[d] != 0u && dig != cur[d]) {
-          atomicAdd(&h[d * kRadix + cur[d]], cnt[d]);
+          atomicAdd(&h[d * kSortRadix + cur[d]], cnt[d]);
           cnt[d] = 0u;
         }
         cur[d] = dig;
@@ -241,14 +269,14 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
   }
 #pragma unroll
   for (int d = 0; d < D; ++d)
-    if (cnt[d]) atomicAdd(&h[d * kRadix + cur[d]], cnt[d]);
+    if (cnt[d]) atomicAdd(&h[d * kSortRadix + cur[d]], cnt[d]);
   if (kGatherRange) acc.publish(range, status);
   __syncthreads();
-  for (int i = threadIdx.x; i < D * kRadix; i += blockDim.x)
+  for (int i = threadIdx.x; i < D * kSortRadix; i += blockDim.x)
     if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
-// One block of 8 waves: wave d scans digit d's 256 counts (4 per lane).
+// One block of 8 waves: wave d scans digit d's counts (kSortRadix / 64 per lane).
 template <class T>
 __global__ __launch_bounds__(512) void k_plan(const uint32_t* __restrict__ hist, int64_t P,
                                               const unsigned long long* __restrict__ range,
@@ -261,23 +289,31 @@ __global__ __launch_bounds__(512) void k_plan(const uint32_t* __restrict__ hist,
   if (b < 8) trivial[b] = 0;
   __syncthreads();
   if (wave < D) {
-    const uint32_t* h = hist + wave * kRadix + 4 * lane;
-    const uint32_t c0 = h[0], c1 = h[1], c2 = h[2], c3 = h[3];
-    if ((int64_t)c0 == P || (int64_t)c1 == P || (int64_t)c2 == P || (int64_t)c3 == P)
-      trivial[wave] = 1;
-    const uint32_t own = c0 + c1 + c2 + c3;
+    constexpr int kPer = kSortRadix / kWave;   // consecutive digit values per lane
+    const uint32_t* h = hist + wave * kSortRadix + kPer * lane;
+    uint32_t c[kPer];
+    uint32_t own = 0u;
+    bool full = false;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      c[q] = h[q];
+      own += c[q];
+      full |= (int64_t)c[q] == P;
+    }
+    if (full) trivial[wave] = 1;
     uint32_t incl = own;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       const uint32_t v = __shfl_up(incl, (unsigned)o, kWave);
       if (lane >= o) incl += v;
     }
-    uint32_t* out = dig_off + wave * kRadix + 4 * lane;
-    const uint32_t e0 = incl - own;
-    out[0] = e0;
-    out[1] = e0 + c0;
-    out[2] = e0 + c0 + c1;
-    out[3] = e0 + c0 + c1 + c2;
+    uint32_t* out = dig_off + wave * kSortRadix + kPer * lane;
+    uint32_t e = incl - own;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      out[q] = e;
+      e += c[q];
+    }
   }
   __syncthreads();
   if (b == 0) {
@@ -289,16 +325,24 @@ __global__ __launch_bounds__(512) void k_plan(const uint32_t* __restrict__ hist,
       pass->code_g = cd.g;
       pass->code_inv_g = cd.inv_g;
     }
-    const int skip = digits_below_resolution<T>(range, res, cd);
+    const DigitLayout L = digit_layout<T>(range, res, cd);
+    // FP32: whole 8-bit digits below the resolution are left unsorted.
+    int skip = 0;
+    if constexpr (sizeof(T) == 4) {
+      int top = 32;
+      skip = resolution_bits<T>(range, res, cd, &top) / 8;
+    }
     for (int d = 0; d < skip; ++d) trivial[d] = 1;
-    pass->skipped_low = skip;
+    pass->skipped_low = L.lo_bit + 8 * skip;
+    pass->bits = L.bits;
     int any = 0;
-    for (int d = 0; d < D; ++d) any |= !trivial[d];
+    for (int d = 0; d < L.passes; ++d) any |= !trivial[d];
     int runs = 0, last_out = 0, last_pass = 0;
     for (int d = 0; d < 8; ++d) {
-      int run = (d < D) && !trivial[d];
-      if (!any && d == D - 1) run = 1;  // all keys equal: one pass materialises them
+      int run = d < L.passes && !trivial[d];
+      if (!any && d == L.passes - 1) run = 1;  // all keys equal: one pass materialises them
       pass->run[d] = run;
+      pass->shift[d] = L.lo_bit + L.bits * d;
       if (run) {
         pass->src[d] = runs == 0 ? kRaw : (runs - 1) % 2;
         last_out = runs % 2;
@@ -322,31 +366,33 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     uint32_t* __restrict__ tile_ctr, uint64_t* lb_cur, uint64_t* lb_next,
     uint32_t* __restrict__ status) {
   using K = typename KeyOf<T>::type;
-  __shared__ uint32_t wcnt[kSortWaves][kRadix];   // per-wave running digit counts, then wave offsets
-  __shared__ uint32_t tstart[kRadix];             // tile-local exclusive digit starts
-  __shared__ uint64_t gbase[kRadix];              // global output position of each digit's run
-  __shared__ uint32_t wsum[kRadix / kWave];
-  __shared__ uint32_t thist[kRadix];               // tile digit histogram
+  __shared__ uint16_t wcnt[kSortWaves][kSortRadix];   // per-wave running digit counts, then wave offsets
+  __shared__ uint32_t tstart[kSortRadix];             // tile-local exclusive digit starts
+  __shared__ uint32_t gbase[kSortRadix];              // global output position of each digit's run
+  __shared__ uint32_t wsum[kSortRadix / kWave];
+  __shared__ uint32_t thist[kSortRadix];               // tile digit histogram
   __shared__ K stage[kSortTile];                  // keys, then (reused) payloads, in digit order
   __shared__ int s_tile;
 
   const int tid = threadIdx.x;
   const int run = pass->run[d];
   const int src = pass->src[d];
+  const int dbits = pass->bits;          // 8 or 9 for the whole sort
+  const int ndig = 1 << dbits;
   if (!run) {
     // Nothing moves; still clear the other look-back buffer for the next pass.
-    if (tid < kRadix)
+    if (tid < ndig)
       for (int64_t t = blockIdx.x; t * kSortTile < P; t += gridDim.x)
-        lb_next[(size_t)t * kRadix + tid] = 0ull;
+        lb_next[(size_t)t * kSortRadix + tid] = 0ull;
     return;
   }
   if (tid == 0) s_tile = (int)atomicAdd(&tile_ctr[d], 1u);
-  for (int i = tid; i < kSortWaves * kRadix; i += kSortThreads) (&wcnt[0][0])[i] = 0u;
-  if (tid < kRadix) thist[tid] = 0u;
+  for (int i = tid; i < kSortWaves * kSortRadix; i += kSortThreads) (&wcnt[0][0])[i] = 0;
+  if (tid < kSortRadix) thist[tid] = 0u;
   __syncthreads();
   const int tile = s_tile;
-  const bool digit_thread = tid < kRadix;   // threads 0..255 own one digit value each
-  if (digit_thread) lb_next[(size_t)tile * kRadix + tid] = 0ull;
+  const bool digit_thread = tid < ndig;   // threads 0..ndig-1 own one digit value each
+  if (digit_thread) lb_next[(size_t)tile * kSortRadix + tid] = 0ull;
 
   const K* kin = src == 1 ? (const K*)keys1 : (const K*)keys0;
   const uint32_t* iin = src == 1 ? idx1 : idx0;
@@ -355,7 +401,8 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
 
   const int wave = tid / kWave;
   const int lane = tid % kWave;
-  const int shift = 8 * d;
+  const int shift = pass->shift[d];
+  const uint32_t mask = (uint32_t)ndig - 1u;
   const int64_t base = (int64_t)tile * kSortTile + (int64_t)wave * (kSortItems * kWave);
 
   K key[kSortItems];
@@ -388,12 +435,12 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   // (longer) stable ranking and successors waiting on them move on sooner.
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i)
-    if (base + i * kWave + lane < P) atomicAdd(&thist[(uint32_t)(key[i] >> shift) & 0xffu], 1u);
+    if (base + i * kWave + lane < P) atomicAdd(&thist[(uint32_t)(key[i] >> shift) & mask], 1u);
   __syncthreads();
   uint32_t tcount = 0u;
   if (digit_thread) {
     tcount = thist[tid];
-    __hip_atomic_store(&lb_cur[(size_t)tile * kRadix + tid], kFlagAgg | (uint64_t)tcount,
+    __hip_atomic_store(&lb_cur[(size_t)tile * kSortRadix + tid], kFlagAgg | (uint64_t)tcount,
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 
@@ -404,20 +451,22 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   for (int i = 0; i < kSortItems; ++i) {
     const int64_t p = base + i * kWave + lane;
     const bool valid = p < P;
-    const uint32_t dig = (uint32_t)(key[i] >> shift) & 0xffu;
+    const uint32_t dig = (uint32_t)(key[i] >> shift) & mask;
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-      const bool on = (dig >> bit) & 1u;
-      const uint64_t bal = __ballot(on);
-      peers &= on ? bal : ~bal;
+    for (int bit = 0; bit < kSortBits; ++bit) {
+      if (bit < dbits) {   // uniform: the last bit only for 9-bit digits
+        const bool on = (dig >> bit) & 1u;
+        const uint64_t bal = __ballot(on);
+        peers &= on ? bal : ~bal;
+      }
     }
     const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
     const uint32_t count = (uint32_t)__popcll(peers);
     const uint32_t before = wcnt[wave][dig];
     __builtin_amdgcn_wave_barrier();
-    if (valid && below == 0u) wcnt[wave][dig] = before + count;
+    if (valid && below == 0u) wcnt[wave][dig] = (uint16_t)(before + count);
     __builtin_amdgcn_wave_barrier();
     rank[i] = before + below;
   }
@@ -441,7 +490,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
 #pragma unroll
       for (int w = 0; w < kSortWaves; ++w) {
         const uint32_t c = wcnt[w][tid];
-        wcnt[w][tid] = run_sum;
+        wcnt[w][tid] = (uint16_t)run_sum;
         run_sum += c;
       }
     }
@@ -457,7 +506,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   uint32_t pos[kSortItems];
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
-    const uint32_t dig = (uint32_t)(key[i] >> shift) & 0xffu;
+    const uint32_t dig = (uint32_t)(key[i] >> shift) & mask;
     pos[i] = tstart[dig] + wcnt[wave][dig] + rank[i];
     if (base + i * kWave + lane < P && pos[i] < (uint32_t)kSortTile) stage[pos[i]] = key[i];
   }
@@ -476,7 +525,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
       uint64_t v[kLookWindow];
 #pragma unroll
       for (int q = 0; q < kLookWindow; ++q) {
-          v[q] = (j - q >= 0) ? __hip_atomic_load(&lb_cur[(size_t)(j - q) * kRadix + tid],
+          v[q] = (j - q >= 0) ? __hip_atomic_load(&lb_cur[(size_t)(j - q) * kSortRadix + tid],
                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                               : kFlagPrefix;
       }
@@ -501,7 +550,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
         uint32_t backoff = 1u;
         uint64_t w;
         while (true) {
-          w = __hip_atomic_load(&lb_cur[(size_t)j * kRadix + tid], __ATOMIC_RELAXED,
+          w = __hip_atomic_load(&lb_cur[(size_t)j * kSortRadix + tid], __ATOMIC_RELAXED,
                                 __HIP_MEMORY_SCOPE_AGENT);
           if ((w & ~kValueMask) != 0ull) break;
           if (++spins > kSpinLimit) break;
@@ -517,9 +566,9 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
         done = (w & ~kValueMask) == kFlagPrefix;
       }
     }
-    __hip_atomic_store(&lb_cur[(size_t)tile * kRadix + tid], kFlagPrefix | (excl + tcount),
+    __hip_atomic_store(&lb_cur[(size_t)tile * kSortRadix + tid], kFlagPrefix | (excl + tcount),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    gbase[tid] = (uint64_t)dig_off[d * kRadix + tid] + excl;
+    gbase[tid] = dig_off[d * kSortRadix + tid] + (uint32_t)excl;
   }
   __syncthreads();
   // Each thread visits the same positions j in both write loops; the output
@@ -535,7 +584,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     outpos[r] = 0xffffffffu;
     if (j < nvalid) {
       const K k = stage[j];
-      const uint32_t dig = (uint32_t)(k >> shift) & 0xffu;
+      const uint32_t dig = (uint32_t)(k >> shift) & mask;
       const uint64_t out = gbase[dig] + (uint64_t)(j - (int)tstart[dig]);
       if (out < (uint64_t)P) {
         outpos[r] = (uint32_t)out;
