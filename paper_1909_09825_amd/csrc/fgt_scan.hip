@@ -248,7 +248,8 @@ __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const
   const int64_t t0 = tile * kScanTile;
 
   {
-    // All of this thread's loads are issued before any is used.
+    // All of this thread's loads are issued before any is used; they are the
+    // last reads of the sorted points in this call, so they are nontemporal.
     constexpr int R = kScanTile / kScanThreads;
     T zr[R], br[R];
     uint32_t sr[R];
@@ -256,9 +257,9 @@ __global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const
     for (int r = 0; r < R; ++r) {
       const int64_t p = t0 + tid + r * kScanThreads;
       const bool in = p < P;
-      zr[r] = in ? keys(p) : T(0);
-      br[r] = in ? bs[p] : T(0);
-      sr[r] = in ? ids[p] : kNoSlot;
+      zr[r] = in ? __builtin_nontemporal_load(&keys.z[p]) : T(0);
+      br[r] = in ? __builtin_nontemporal_load(&bs[p]) : T(0);
+      sr[r] = in ? __builtin_nontemporal_load(&ids[p]) : kNoSlot;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -452,7 +453,8 @@ __global__ __launch_bounds__(kScanThreads) void k_final_fast(
   const int n = (int)((P - t0) < kScanTile ? (P - t0) : kScanTile);
 
   {
-    // All of this thread's loads are issued before any is used.
+    // All of this thread's loads are issued before any is used; they are the
+    // last reads of the sorted points in this call, so they are nontemporal.
     constexpr int R = kScanTile / kScanThreads;
     T zr[R], br[R];
     uint32_t sr[R];
@@ -460,9 +462,9 @@ __global__ __launch_bounds__(kScanThreads) void k_final_fast(
     for (int r = 0; r < R; ++r) {
       const int64_t p = t0 + tid + r * kScanThreads;
       const bool in = p < P;
-      zr[r] = in ? keys(p) : T(0);
-      br[r] = in ? bs[p] : T(0);
-      sr[r] = in ? ids[p] : kNoSlot;
+      zr[r] = in ? __builtin_nontemporal_load(&keys.z[p]) : T(0);
+      br[r] = in ? __builtin_nontemporal_load(&bs[p]) : T(0);
+      sr[r] = in ? __builtin_nontemporal_load(&ids[p]) : kNoSlot;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {

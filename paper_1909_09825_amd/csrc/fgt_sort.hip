@@ -408,26 +408,39 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   K key[kSortItems];
   uint32_t id[kSortItems];
   uint32_t rank[kSortItems];
-  // Two separate load loops (the source is the same for the whole pass), each
-  // issuing all of its loads before any is used.
+  // Separate load loops (the source is the same for the whole pass), each
+  // issuing all of its loads before any is used.  The points of the first pass
+  // and the keys of the middle passes are read once: nontemporal loads keep
+  // them from displacing the lines in which the scattered runs of the pass are
+  // being written.  The last pass loads normally (nontemporal measured slower
+  // there).
   if (src == kRaw) {
     T z[kSortItems];
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
       const int64_t p = base + i * kWave + lane;
-      z[i] = p < P ? load_point(x, y, N, p) : T(0);
+      z[i] = p >= P ? T(0)
+           : p < N  ? __builtin_nontemporal_load(&y[p])
+                    : __builtin_nontemporal_load(&x[p - N]);
       id[i] = p < P ? (uint32_t)p : 0u;
     }
     const Codec<T> cd = codec_of<T>(pass);
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i)
       key[i] = base + i * kWave + lane < P ? cd.encode(z[i]) : (K)0;
-  } else {
+  } else if (d == pass->last_pass) {
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
       const int64_t p = base + i * kWave + lane;
       key[i] = p < P ? kin[p] : (K)0;
       id[i] = p < P ? iin[p] : 0u;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+      const int64_t p = base + i * kWave + lane;
+      key[i] = p < P ? __builtin_nontemporal_load(&kin[p]) : (K)0;
+      id[i] = p < P ? __builtin_nontemporal_load(&iin[p]) : 0u;
     }
   }
 
