@@ -257,6 +257,8 @@ union AdjFastLds {
 };
 
 // Loads this thread's share of the tile into LDS (coalesced), all loads first.
+// These are the last reads of the sorted arrays in the call, so they are
+// nontemporal: they leave the caches to the scattered gradient writes.
 template <class T>
 __device__ __forceinline__ void stage_tile(Staged2<T>& st, const KeyView<T>& keys, const T* b,
                                            const T* bt, const uint32_t* ids, int64_t t0,
@@ -269,10 +271,10 @@ __device__ __forceinline__ void stage_tile(Staged2<T>& st, const KeyView<T>& key
   for (int r = 0; r < R; ++r) {
     const int64_t p = t0 + tid + r * kScanThreads;
     const bool in = p < P;
-    zr[r] = in ? keys(p) : T(0);
-    br[r] = in ? b[p] : T(0);
-    gr[r] = in ? bt[p] : T(0);
-    ir[r] = in ? ids[p] : kNoSlot;
+    zr[r] = in ? __builtin_nontemporal_load(&keys.z[p]) : T(0);
+    br[r] = in ? __builtin_nontemporal_load(&b[p]) : T(0);
+    gr[r] = in ? __builtin_nontemporal_load(&bt[p]) : T(0);
+    ir[r] = in ? __builtin_nontemporal_load(&ids[p]) : kNoSlot;
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
