@@ -79,7 +79,8 @@ __global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void*
 #pragma unroll
     for (int m = 0; m <= kMomentMax; ++m) mu[m] = T(0);
     // The lane's points in order, kGrp at a time with all their loads issued
-    // before any is used.
+    // before any is used.  The loads are nontemporal: the final kernel reads
+    // these arrays again, but they are far larger than the caches.
     constexpr int kGrp = 8;
 #pragma unroll 1
     for (int g0 = 0; g0 < kScanTile / kWave; g0 += kGrp) {
@@ -88,8 +89,8 @@ __global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void*
       for (int i = 0; i < kGrp; ++i) {
         const int e = lane + (g0 + i) * kWave;
         const bool in = e < n;
-        zg[i] = in ? keys(t0 + e) : c;
-        bg[i] = in ? bs[t0 + e] : T(0);
+        zg[i] = in ? __builtin_nontemporal_load(&keys.z[t0 + e]) : c;
+        bg[i] = in ? __builtin_nontemporal_load(&bs[t0 + e]) : T(0);
       }
 #pragma unroll
       for (int i = 0; i < kGrp; ++i) {
