@@ -785,21 +785,19 @@ __global__ __launch_bounds__(kBThreads) void k_bscan(
       if (cw < kCW - 1) cb = cfma(xr.a, cb, xr.g);
 
       const double om_re = md.om_re[k], om_im = md.om_im[k];
-      C<double> hh = cf;
+      // Both sweeps in one loop (forward step j, backward step CH-1-j): the two
+      // chains of dependent complex FMAs are independent and interleave.
+      C<double> hh = cf, g = cb;
 #pragma unroll
       for (int j = 0; j < CH; ++j) {
-        const int e = chunk * CH + j;
+        const int jb = CH - 1 - j;
+        const int e = chunk * CH + j, eb = chunk * CH + jb;
         const C<double> ex = {s_ex[2 * expad<CH>(e)], s_ex[2 * expad<CH>(e) + 1]};
+        const C<double> exb = {s_ex[2 * expad<CH>(eb)], s_ex[2 * expad<CH>(eb) + 1]};
         hh = cfma(ex, hh, C<double>{b[j], 0.0});
         acc[j] = fma(om_re, hh.re, fma(-om_im, hh.im, acc[j]));
-      }
-      C<double> g = cb;
-#pragma unroll
-      for (int j = CH - 1; j >= 0; --j) {
-        const int e = chunk * CH + j;
-        const C<double> ex = {s_ex[2 * expad<CH>(e)], s_ex[2 * expad<CH>(e) + 1]};
-        acc[j] = fma(om_re, g.re, fma(-om_im, g.im, acc[j]));
-        g = cmul(ex, cadd(g, C<double>{b[j], 0.0}));
+        acc[jb] = fma(om_re, g.re, fma(-om_im, g.im, acc[jb]));
+        g = cmul(exb, cadd(g, C<double>{b[jb], 0.0}));
       }
     }
     __syncthreads();   // s_ex and s_wt are rewritten for the next mode
