@@ -165,11 +165,16 @@ def soe_value(tau0: np.ndarray, omega: np.ndarray, x: np.ndarray) -> np.ndarray:
     return out
 
 
-def table_errors(tau0: np.ndarray, omega: np.ndarray, x: np.ndarray | None = None):
+def table_errors(tau0: np.ndarray, omega: np.ndarray, x: np.ndarray | None = None,
+                 plant: int = 0):
     """(E_n, E'_n, max |Im S|) on the (3.1) grid at delta = 1.
 
-    E'_n = max_{x > 0} |S_n'(x) - G'(x)| with S_n' = -Re sum omega tau0 e^{-tau0 x}
-    and G' = -(x/2) e^{-x^2/4}.
+    E'_n = sup_{x > 0} |S_n'(x) - G'(x)| with S_n' = -Re sum omega tau0 e^{-tau0 x}
+    and G' = -(x/2) e^{-x^2/4}: the maximum over the grid's positive points and
+    the one-sided limit x -> 0+, where G'(0) = 0 and S_n'(0+) = -Re sum omega tau0
+    (the cusp of the SOE at the origin).  `plant` selects a deliberately wrong
+    E'_n (tests only): 1 takes the complex modulus instead of the real part,
+    2 drops the factor tau0 of the derivative.
     """
     if x is None:
         x = paper_grid()
@@ -179,9 +184,14 @@ def table_errors(tau0: np.ndarray, omega: np.ndarray, x: np.ndarray | None = Non
     xp = x[x > 0]
     ds = np.zeros(xp.shape, dtype=np.complex128)
     for tk, wk in zip(tau0, omega):
-        ds += -wk * tk * np.exp(-tk * xp)
+        ds += -wk * (tk if plant != 2 else 1.0) * np.exp(-tk * xp)
     dg = -(xp / 2.0) * np.exp(-xp * xp / 4.0)
-    ep = float(np.max(np.abs(ds.real - dg)))
+    if plant == 1:
+        ep = float(np.max(np.abs(ds - dg)))
+    else:
+        ep = float(np.max(np.abs(ds.real - dg)))
+    cusp = abs(float(np.sum(np.asarray(omega) * np.asarray(tau0)).real))
+    ep = max(ep, cusp)
     return e, ep, float(np.max(np.abs(s.imag)))
 
 

@@ -21,7 +21,7 @@ import torch
 import oracle
 import paper_1909_09825_amd as fgt
 from paper_1909_09825_amd import workloads as W
-from fgt_testlib import EPS32, EPS64, impl_tol, oracle_table, say, to_dev
+from fgt_testlib import EPS32, EPS64, impl_tol, oracle_E, oracle_Eprime, oracle_table, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +30,7 @@ def impl_tol_der(w, p, P, eps=EPS64):
     """Rounding tolerance of a derivative field: impl_tol with |tau_k omega_k| in place of |omega_k|."""
     s_w = float(np.sum(np.abs(w)))
     s_dom = float(np.sum(np.abs(p.tau * p.omega)))
-    tie = 2.0 * p.deriv_err_bound / math.sqrt(p.delta) * 1e-6 * s_w
+    tie = 2.0 * oracle_Eprime(p) / math.sqrt(p.delta) * 1e-6 * s_w
     return 64.0 * eps * s_w * s_dom * max(1.0, math.log2(max(P, 2))) + tie
 
 
@@ -91,8 +91,8 @@ def check_all(got, x, y, a, g, p, eps=EPS64, soe=True, factor=2.0, case=""):
             f"ddelta {e[3]:.2e}")
         assert max(e) <= 1.0
     o_da, o_dx, o_dy, o_dd = oracle.direct_gradients(x, y, a, g, delta)
-    ep = p.deriv_err_bound / rd
-    r = [np.max(np.abs(da - o_da)) / (factor * p.err_bound * sg + impl_tol(g, p, P, eps)),
+    ep = oracle_Eprime(p) / rd
+    r = [np.max(np.abs(da - o_da)) / (factor * oracle_E(p) * sg + impl_tol(g, p, P, eps)),
          np.max(np.abs(dx - o_dx) / (np.abs(g) * (factor * ep * sa + impl_tol_der(a, p, P, eps)) + 1e-300)),
          np.max(np.abs(dy - o_dy) / (np.abs(a) * (factor * ep * sg + impl_tol_der(g, p, P, eps)) + 1e-300)),
          abs(dd - o_dd) / (factor * e_second(p) / (2 * delta) * sa * sg)]
@@ -181,8 +181,8 @@ def test_grad_all_points_equal():
     a, g = g0.standard_normal(N), g0.standard_normal(M)
     (da, dx, dy, dd), _, p, st = gpu_backward(x, y, a, g, 1e-2, 6, case="all-equal")
     assert st == fgt.FGT_OK
-    np.testing.assert_allclose(da, np.full(N, g.sum()), rtol=0, atol=2 * p.err_bound * np.abs(g).sum())
-    ep = p.deriv_err_bound / 0.1
+    np.testing.assert_allclose(da, np.full(N, g.sum()), rtol=0, atol=2 * oracle_E(p) * np.abs(g).sum())
+    ep = oracle_Eprime(p) / 0.1
     assert np.all(np.abs(dx) <= np.abs(g) * ep * np.abs(a).sum())
     assert np.all(np.abs(dy) <= np.abs(a) * ep * np.abs(g).sum())
 
@@ -254,7 +254,7 @@ def test_autograd_partial_requirements():
     u.sum().backward()
     ref = oracle.direct(y, x, np.ones(M), 1e-3)
     p = fgt.plan(1e-3, 6)
-    assert np.max(np.abs(A.grad.cpu().numpy() - ref)) <= 2 * p.err_bound * M
+    assert np.max(np.abs(A.grad.cpu().numpy() - ref)) <= 2 * oracle_E(p) * M
 
 
 def test_gradcheck_tiny():
@@ -308,8 +308,8 @@ def test_grad_full_size_fp64():
     sj = W.sample_indices(pr.N, 4096, cfg=5, sub=2)
     o_da, o_dx, o_dy, _ = oracle.direct_gradients(pr.x, pr.y, pr.alpha, g, delta, targets=ti, sources=sj)
     sa, sg = np.abs(pr.alpha).sum(), np.abs(g).sum()
-    ep = p.deriv_err_bound / math.sqrt(delta)
-    r1 = np.max(np.abs(da[sj] - o_da)) / (2 * p.err_bound * sg)
+    ep = oracle_Eprime(p) / math.sqrt(delta)
+    r1 = np.max(np.abs(da[sj] - o_da)) / (2 * oracle_E(p) * sg)
     r2 = np.max(np.abs(dx[ti] - o_dx) / (np.abs(g[ti]) * 2 * ep * sa))
     r3 = np.max(np.abs(dy[sj] - o_dy) / (np.abs(pr.alpha[sj]) * 2 * ep * sg))
     say(f"   vs direct gradients (4096 sampled), err/bound: dalpha {r1:.3e} dx {r2:.3e} dy {r3:.3e}")
@@ -348,13 +348,13 @@ def test_grad_full_size_fp32_4digits():
     sj = W.sample_indices(pr.N, 4096, cfg=5, sub=4)
     o_da, o_dx, o_dy, _ = oracle.direct_gradients(x32, y32, a32, g32, delta, targets=ti, sources=sj)
     sa, sg = np.abs(a32).sum(), np.abs(g32).sum()
-    ep = p.deriv_err_bound / math.sqrt(delta)
+    ep = oracle_Eprime(p) / math.sqrt(delta)
     m1 = np.max(np.abs(da[sj] - o_da)) / sg
     m2 = np.max(np.abs(dx[ti] - o_dx) / np.abs(g32[ti])) / (sa / math.sqrt(delta))
     m3 = np.max(np.abs(dy[sj] - o_dy) / np.abs(a32[sj])) / (sg / math.sqrt(delta))
-    say(f"   fp32 4 digits, measured max err: dalpha {m1:.3e} x sum|g| (E {p.err_bound:.2e}); "
-        f"dx {m2:.3e}, dy {m3:.3e} x sum|w|/sqrt(delta) (E' {p.deriv_err_bound:.2e})")
-    r1 = np.max(np.abs(da[sj] - o_da)) / (2 * p.err_bound * sg + impl_tol(g32, p, P, EPS32))
+    say(f"   fp32 4 digits, measured max err: dalpha {m1:.3e} x sum|g| (E {oracle_E(p):.2e}); "
+        f"dx {m2:.3e}, dy {m3:.3e} x sum|w|/sqrt(delta) (E' {oracle_Eprime(p):.2e})")
+    r1 = np.max(np.abs(da[sj] - o_da)) / (2 * oracle_E(p) * sg + impl_tol(g32, p, P, EPS32))
     r2 = np.max(np.abs(dx[ti] - o_dx) / (np.abs(g32[ti]) * (2 * ep * sa + impl_tol_der(a32, p, P, EPS32))))
     r3 = np.max(np.abs(dy[sj] - o_dy) / (np.abs(a32[sj]) * (2 * ep * sg + impl_tol_der(g32, p, P, EPS32))))
     assert max(r1, r2, r3) <= 1.0

@@ -17,7 +17,7 @@ import torch
 import oracle
 import paper_1909_09825_amd as fgt
 from paper_1909_09825_amd import workloads as W
-from fgt_testlib import EPS32, check_direct, gpu_eval, impl_tol, oracle_table, say
+from fgt_testlib import EPS32, check_direct, gpu_eval, impl_tol, oracle_E, oracle_table, say
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,7 @@ def test_large_uniform(delta, digits):
     assert st == fgt.FGT_OK
     idx = W.sample_indices(pr.M, SAMPLES[delta], cfg=2, sub=int(digits))
     e1, _ = check_direct(u[idx], pr.x[idx], pr.y, pr.alpha, delta, p)
-    assert e1 <= 2 * p.err_bound
+    assert e1 <= 2 * oracle_E(p)
     if digits == 6:
         t = oracle_table(p)
         u2 = oracle.soe_recurrence(pr.x, pr.y, pr.alpha, delta, t["tau0"], t["omega"])
@@ -79,7 +79,7 @@ def test_clustered_fp64(digits):
     assert st == fgt.FGT_OK
     idx = np.union1d(W.sample_indices(pr.M, 2048, cfg=3, sub=digits), cluster_targets(pr))
     e1, _ = check_direct(u[idx], pr.x[idx], pr.y, pr.alpha, pr.delta, p)
-    assert e1 <= 2 * p.err_bound
+    assert e1 <= 2 * oracle_E(p)
     if digits == 6:
         t = oracle_table(p)
         u2 = oracle.soe_recurrence(pr.x, pr.y, pr.alpha, pr.delta, t["tau0"], t["omega"])
@@ -105,7 +105,7 @@ def test_clustered_fp32(digits):
     err = float(np.max(np.abs(u[idx] - ref))) / s_alpha
     ref64 = oracle.direct(pr.x[idx], pr.y, pr.alpha, pr.delta)
     err64 = float(np.max(np.abs(u[idx] - ref64))) / float(np.sum(np.abs(pr.alpha)))
-    bound = p.err_bound + 64 * EPS32 * float(np.sum(np.abs(p.omega)))
+    bound = oracle_E(p) + 64 * EPS32 * float(np.sum(np.abs(p.omega)))
     say(f"   FP32 error / sum|alpha| = {err:.3e} vs rounded inputs, {err64:.3e} vs FP64 inputs "
-        f"(E = {p.err_bound:.2e}, bound {bound:.2e})")
+        f"(E = {oracle_E(p):.2e}, bound {bound:.2e})")
     assert err <= bound

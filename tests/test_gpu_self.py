@@ -12,7 +12,7 @@ import torch
 import oracle
 import paper_1909_09825_amd as fgt
 from paper_1909_09825_amd import workloads as W
-from fgt_testlib import EPS32, impl_tol, oracle_table, say, to_dev
+from fgt_testlib import EPS32, impl_tol, oracle_E, oracle_table, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -41,8 +41,8 @@ def test_self_uniform(delta, digits):
     ref2 = oracle.soe_recurrence(x, x, a, delta, t["tau0"], t["omega"])
     e2 = np.max(np.abs(u - ref2))
     tol = impl_tol(a, p, N)
-    say(f"   O1 err / sum|alpha| = {e1:.3e} (2E = {2 * p.err_bound:.3e}); O2 err {e2:.3e} (tol {tol:.3e})")
-    assert e1 <= 2 * p.err_bound and e2 <= tol
+    say(f"   O1 err / sum|alpha| = {e1:.3e} (2E = {2 * oracle_E(p):.3e}); O2 err {e2:.3e} (tol {tol:.3e})")
+    assert e1 <= 2 * oracle_E(p) and e2 <= tol
 
 
 def test_self_matches_general_path():
@@ -64,7 +64,7 @@ def test_self_chebyshev_presorted(N):
     assert st1 == fgt.FGT_OK and st2 == fgt.FGT_OK
     np.testing.assert_array_equal(u1, u2)
     ref = oracle.direct(x, x, a, 1e-4)
-    assert np.max(np.abs(u1 - ref)) / np.abs(a).sum() <= 2 * p.err_bound
+    assert np.max(np.abs(u1 - ref)) / np.abs(a).sum() <= 2 * oracle_E(p)
 
 
 def test_self_presorted_flag_checks_order():
@@ -85,8 +85,8 @@ def test_self_fp32_and_ties():
     assert st == fgt.FGT_OK
     ref = oracle.direct(x32, x32, a32, 1e-4)
     err = np.max(np.abs(u - ref)) / np.abs(a32).sum()
-    say(f"   fp32 err / sum|alpha| = {err:.3e} (E = {p.err_bound:.3e})")
-    assert err <= 2 * p.err_bound + impl_tol(a32, p, N, EPS32) / np.abs(a32).sum()
+    say(f"   fp32 err / sum|alpha| = {err:.3e} (E = {oracle_E(p):.3e})")
+    assert err <= 2 * oracle_E(p) + impl_tol(a32, p, N, EPS32) / np.abs(a32).sum()
 
 
 def test_self_empty():

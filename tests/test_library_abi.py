@@ -115,6 +115,20 @@ def test_stated_bound_is_honest(digits):
     assert max(ep, ep2) <= p.deriv_err_bound * 1.01
 
 
+@pytest.mark.parametrize("digits", [1, 3, 4, 5, 6, 8, 9, 10, 11])
+def test_stated_bounds_sit_on_the_oracles(otables, digits):
+    """The plan states E_n and E'_n from its own generator; they may carry a
+    small margin over the oracle's measurement but not inflate it: every GPU
+    parity bar takes the oracle's values, and this keeps the two within
+    [1, 1.002] (E_n) and [1, 1.02] (E'_n) of each other.  The table the plan
+    picks for `digits` is the one the oracle's reading of "digits" picks."""
+    p = fgt.plan(1.0, digits)
+    assert soe_table.modes_for_digits(otables, digits) == p.n_modes
+    t = otables[p.n_modes]
+    assert t["E"] <= p.err_bound <= 1.002 * t["E"], (p.err_bound, t["E"])
+    assert t["Eprime"] <= p.deriv_err_bound <= 1.02 * t["Eprime"], (p.deriv_err_bound, t["Eprime"])
+
+
 def test_backward_and_eval_sorted_validation():
     lib = _lib.load()
     h = ctypes.c_void_p()

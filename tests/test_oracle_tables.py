@@ -128,3 +128,62 @@ def test_digit_claims(otables, paper):
     assert ST.modes_for_digits(otables, 3) == 2
     assert ST.modes_for_digits(otables, 6) == 4
     assert ST.modes_for_digits(otables, 9) == 6
+
+
+# ---------------------------------------------------------------------------
+# E'_n pinned from both sides by a route other than the derivative formula:
+# slopes of the error function eps(x) = S_n(x) - G(x) itself, taken as forward
+# difference quotients in mpmath (step 1e-20 at 50 digits, so the quotient is
+# the derivative to ~1e-17 absolute).  By the mean value theorem every quotient
+# is a value of eps', so their maximum is a lower bound of sup|eps'|; on a grid
+# this dense (and at x = 0, where the quotient is the one-sided slope of the
+# cusp, G'(0) = 0) it is also within a fraction of a percent of it.  A planted
+# inflation of E'_n (the complex modulus instead of the real part, or a dropped
+# factor tau0) misses the window by orders of magnitude.
+# ---------------------------------------------------------------------------
+def fd_slope_sup(tau0, omega, dps=50):
+    with mp.workdps(dps):
+        ts = [mp.mpc(complex(t)) for t in tau0]
+        ws = [mp.mpc(complex(w)) for w in omega]
+        h = mp.mpf("1e-20")
+
+        def eps(x):
+            return mp.re(mp.fsum(w * mp.exp(-t * x) for t, w in zip(ts, ws))) - mp.exp(-x * x / 4)
+
+        xs = ([mp.mpf(0)] + [mp.mpf(float(v)) for v in np.linspace(0.002, 2.0, 1000)]
+              + [mp.mpf(float(v)) for v in np.linspace(2.01, 30.0, 2800)])
+        return float(max(abs((eps(x + h) - eps(x)) / h) for x in xs))
+
+
+FD_SUP = {}
+
+
+def _fd(otables, m):
+    if m not in FD_SUP:
+        FD_SUP[m] = fd_slope_sup(otables[m]["tau0"], otables[m]["omega"])
+    return FD_SUP[m]
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6, 7])
+def test_deriv_error_pinned_by_slopes(otables, m):
+    fd = _fd(otables, m)
+    ep = otables[m]["Eprime"]
+    assert fd * (1 - 1e-6) <= ep <= fd * 1.005, (ep, fd)
+
+
+@pytest.mark.parametrize("plant", [1, 2])
+@pytest.mark.parametrize("m", [2, 4, 6])
+def test_planted_deriv_error_is_caught(otables, m, plant):
+    t = otables[m]
+    _, ep, _ = ST.table_errors(t["tau0"], t["omega"], plant=plant)
+    fd = _fd(otables, m)
+    assert not (fd * (1 - 1e-6) <= ep <= fd * 1.005), (plant, ep, fd)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6])
+def test_deriv_error_is_the_cusp(otables, m):
+    """Up to 6 modes the largest slope error sits at the origin: E'_n = |Re sum omega tau0|."""
+    t = otables[m]
+    cusp = abs(float(np.sum(t["omega"] * t["tau0"]).real))
+    assert t["Eprime"] == pytest.approx(cusp, rel=1e-12)
+    assert _fd(otables, m) == pytest.approx(cusp, rel=1e-6)
