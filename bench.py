@@ -17,10 +17,18 @@ transform and column) timed on 32 of the transforms and scaled to 4096.
 sort skipped).  `identical_points` times fgt_eval_self in the setting of the
 paper's Table 1 (targets = sources, N = 10^7 uniform on [0,1), delta = 1,
 n_e = 3..6), with Chebyshev points in order and the sort skipped beside it.
-`roofline` describes
-the kernel with the largest share of the step, timed with HIP events recorded
-by the library on its own stream during the timed steps; `cpu_baseline` is
-the CPU oracle's SOE recurrence timed on a bounded sample of the same inputs.
+`small` gives the latency
+of one transform at M = N = 1000 (delta 1e-3, 6 digits), eager and as a
+replayed HIP graph; `clustered` the 2^24-source Gaussian-mixture case with
+2^22 uniform targets (delta 1e-5, FP64 and FP32 at 6 digits); `differentiation`
+forward against forward + adjoint at M = N = 2^22 (delta 1e-4, FP64 at 9 digits,
+FP32 at 4 digits).  Every time is the wall clock over the timed calls
+(synchronised on both sides) next to the median of per-call HIP events.
+`roofline` describes the kernel with the largest share of the step, timed with
+HIP events that the library records on its own stream during the timed steps;
+`cpu_baseline` is the CPU oracle's SOE recurrence timed on a bounded sample of
+the same inputs, on one thread and on all of the host's cores, with and
+without its sort.
 
     python bench.py [--steps K] [--warmup W] [--delta D] [--digits G] [--log2n L]
 """
@@ -30,14 +38,20 @@ import argparse
 import json
 import math
 import os
+import platform
+import statistics
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
+# VALU issue slots: 256 CUs x 4 SIMDs at 2.4 GHz; a wave64 VALU instruction
+# occupies a 16-lane SIMD for 4 cycles (FP64 FMA at the 78.6 TFLOP/s peak).
+VALU_SLOTS_PER_S = 256 * 4 * 2.4e9 / 4
 METRIC = "(M+N)·modes/s and transforms/s at 6 digits, fwd vs fwd+bwd, % HBM roofline"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_counters.json")
 
 
 def parse():
@@ -56,42 +70,103 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched timing")
     ap.add_argument("--no-identical", action="store_true",
                     help="skip the identical-points (Table 1 setting) timing")
+    ap.add_argument("--no-small", action="store_true", help="skip the M = N = 1000 latency")
+    ap.add_argument("--no-clustered", action="store_true", help="skip the clustered workload")
+    ap.add_argument("--no-diff", action="store_true", help="skip the 2^22 differentiation rows")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one plain device copy of this many bytes (counter calibration)")
     return ap.parse_args()
 
 
-def traffic_for(kernel: str):
-    """HBM bytes per launch from committed counter runs, if the kernel source is unchanged."""
+def _counter_record(path, kernel):
+    """A committed per-kernel counter record, if the kernel's sources are unchanged."""
     from paper_1909_09825_amd.profiling import source_hash
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             rec = json.load(f).get(kernel)
     except (OSError, ValueError):
         return None
     if not rec or rec.get("source_sha") != source_hash(rec["sources"]):
         return None
-    return int(rec["bytes_per_launch"])
+    return rec
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch from committed counter runs, if the kernel source is unchanged."""
+    rec = _counter_record(TRAFFIC_FILE, kernel)
+    return int(rec["bytes_per_launch"]) if rec else None
+
+
+def valu_frac(kernel: str, ms_launch: float):
+    """Fraction of the chip's VALU issue slots used: committed SQ_INSTS_VALU per
+    launch (wave instructions, 4 cycles each) over the launch's measured time."""
+    rec = _counter_record(VALU_FILE, kernel)
+    if not rec or ms_launch <= 0:
+        return None
+    return round(float(rec["valu_insts_per_launch"]) / (ms_launch * 1e-3 * VALU_SLOTS_PER_S), 4)
+
+
+def timed(fn, steps, warmup, torch):
+    """Warm up, then run `steps` calls: wall clock over all of them (synchronised
+    on both sides) and the median of per-call HIP events on the current stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    return wall, statistics.median(a.elapsed_time(b) for a, b in evs)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 def cpu_baseline(x, y, a, delta, digits, n_modes, k):
-    """The CPU oracle's SOE recurrence (sort + per-mode sweeps) on the first 2^k points."""
+    """The CPU oracle's SOE recurrence (sort + per-mode sweeps) on the first 2^k
+    targets and sources: one thread and all of the host's cores (OpenMP over the
+    2 n_e sweeps), each with and without the sort (the paper's t_total and t_linear)."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import oracle
     from conftest import load_oracle_tables
     t = load_oracle_tables()[n_modes]
     n = 1 << k
     xs, ys, as_ = x[:n].copy(), y[:n].copy(), a[:n].copy()
-    t0 = time.perf_counter()
-    oracle.soe_recurrence(xs, ys, as_, delta, t["tau0"], t["omega"])
-    dt = time.perf_counter() - t0
-    threads = oracle.max_threads()
+    work = (2 * n) * n_modes
+    legs = {}
+    all_threads = oracle.max_threads()
+    for name, threads in (("one_core", 1), ("all_cores", all_threads)):
+        t0 = time.perf_counter()
+        oracle.soe_recurrence(xs, ys, as_, delta, t["tau0"], t["omega"], threads=threads)
+        dt = time.perf_counter() - t0
+        ts = oracle.last_sort_seconds()
+        legs[name] = {"threads": threads, "s_total": round(dt, 3), "s_sort": round(ts, 3),
+                      "with_sort": work / dt, "without_sort": work / max(dt - ts, 1e-9)}
     return {
-        "value": (2 * n) * n_modes / dt, "unit": "point-modes/s",
-        "cores": int(min(threads, 2 * n_modes)), "kind": "oracle",
+        "value": legs["all_cores"]["with_sort"], "unit": "point-modes/s",
+        "cores": all_threads, "kind": "oracle",
         "sample": (f"first 2^{k} targets and 2^{k} sources of the same inputs, {digits} digits "
                    f"({n_modes} modes): O2 SOE recurrence in C (qsort, then one sweep per mode and "
-                   f"direction, OpenMP over the {2 * n_modes} sweeps), {dt:.2f} s wall"),
+                   f"direction, OpenMP over the {2 * n_modes} sweeps), "
+                   f"{legs['all_cores']['s_total']:.2f} s wall on {all_threads} threads"),
+        "host": {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+                 "omp_threads": all_threads, "cpu": cpu_model()},
+        "one_core": legs["one_core"],
+        "all_cores": legs["all_cores"],
     }
 
 
@@ -147,11 +222,8 @@ def bench_batched(args, fgt, W, torch, np, dev):
     torch.cuda.synchronize()
     if fgt.last_device_status(ws) != fgt.FGT_OK:
         raise RuntimeError("device status after batched warmup")
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        fgt.eval_batch(X, Y, A, bp, out=U, ws=ws)
-    torch.cuda.synchronize()
-    ms_eager = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms_eager, ms_med = timed(lambda: fgt.eval_batch(X, Y, A, bp, out=U, ws=ws), args.steps, 0,
+                             torch)
     # the same launch sequence captured once and replayed
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -190,24 +262,159 @@ def bench_batched(args, fgt, W, torch, np, dev):
     pts32 = sum(int(c[1].shape[0] + c[2].shape[0]) for c in calls)
     ms_loop = ms_loop32 * bp.total_points / pts32
     ms = min(ms_eager, ms_graph)
+    # Roofline of the whole batch: every coordinate read once, alpha and u
+    # (R columns) read and written once; VALU from the per-point-mode count of
+    # one complex exponential (~50 lane-operations) and R columns of two
+    # complex FMA sweeps plus the accumulation (~10 each).
+    P = bp.total_points
+    alg_bytes = 8 * P + 8 * R * (bp.N + bp.M)
+    valu_ops = P * bp.n_modes * (50 + R * 10)
+    cpu = batched_cpu_baseline(bt, bp.n_modes) if not args.no_cpu_baseline else None
     return {
         "workload": (f"{B} transforms, N_b and M_b log-uniform in [256, 65536], delta_b "
                      f"log-uniform in [1e-6, 1e-2], points uniform on [0,1), alpha [N][{R}] ~ N(0,1), "
                      f"{bt.digits} digits ({bp.n_modes} modes), FP64"),
-        "total_points": bp.total_points,
+        "total_points": P,
         "ms_per_batch_eager": round(ms_eager, 4),
         "ms_per_batch_graph": round(ms_graph, 4),
+        "ms_median_event": round(ms_med, 4),
         "transforms_per_s": B / (ms * 1e-3),
         "column_transforms_per_s": B * R / (ms * 1e-3),
-        "value": bp.total_points * bp.n_modes * R / (ms * 1e-3),
+        "value": P * bp.n_modes * R / (ms * 1e-3),
         "unit": "point-mode-columns/s",
+        "roofline": {"alg_bytes": int(alg_bytes), "hbm_frac": round(alg_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                     "valu_ops_model": int(valu_ops),
+                     "valu_frac_model": round(valu_ops / (ms * 1e-3) / (FP64_VALU_PEAK_TFLOPS * 1e12 / 2), 4)},
         "loop_of_fgt_eval_ms": round(ms_loop, 2),
         "loop_sample": (f"fgt_eval once per column on 32 sampled transforms ({pts32} points), "
                         f"{ms_loop32:.1f} ms, scaled by total points"),
         "speedup_vs_loop": round(ms_loop / ms, 1),
         "tuned_config": {"points_per_lane": config[0], "bucket_points": config[1],
                          "tuning_s": round(tune_s, 2)},
+        "cpu_baseline": cpu,
     }
+
+
+def batched_cpu_baseline(bt, n_modes, n_pick=24):
+    """The oracle's SOE recurrence, column by column, on a sample of the batch's
+    transforms (all host threads, OpenMP over each call's sweeps)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import numpy as np
+    import oracle
+    from conftest import load_oracle_tables
+    t = load_oracle_tables()[n_modes]
+    picks = np.random.default_rng(7).choice(len(bt.delta), n_pick, replace=False)
+    R = bt.alpha.shape[1]
+    pts = 0
+    t0 = time.perf_counter()
+    for b in picks:
+        xs, xe, ys, ye = (int(bt.x_off[b]), int(bt.x_off[b + 1]), int(bt.y_off[b]),
+                          int(bt.y_off[b + 1]))
+        for r in range(R):
+            oracle.soe_recurrence(bt.x[xs:xe], bt.y[ys:ye], bt.alpha[ys:ye, r],
+                                  float(bt.delta[b]), t["tau0"], t["omega"])
+        pts += (xe - xs) + (ye - ys)
+    dt = time.perf_counter() - t0
+    return {"value": pts * n_modes * R / dt, "unit": "point-mode-columns/s",
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{n_pick} sampled transforms x {R} columns ({pts} points), {dt:.2f} s wall"}
+
+
+def bench_small(args, fgt, W, torch, np, dev):
+    """M = N = 1000 (delta 1e-3, 6 digits): latency per transform."""
+    pr = W.small_plain()
+    p = fgt.plan(pr.delta, pr.digits)
+    X, Y, A = (torch.from_numpy(v).to(dev) for v in (pr.x, pr.y, pr.alpha))
+    ws = fgt.workspace(p, pr.M, pr.N, dev)
+    u = torch.empty(pr.M, dtype=torch.float64, device=dev)
+    steps = max(args.steps, 200)
+    wall, med = timed(lambda: fgt.eval(X, Y, A, p, out=u, ws=ws), steps, 10, torch)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fgt.eval(X, Y, A, p, out=u, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fgt.eval(X, Y, A, p, out=u, ws=ws)
+    gwall, gmed = timed(graph.replay, steps, 10, torch)
+    if fgt.last_device_status(ws) != fgt.FGT_OK:
+        raise RuntimeError("device status after the small workload")
+    return {"workload": "M = N = 1000 uniform on [0,1), alpha ~ N(0,1), delta = 1e-3, 6 digits, FP64",
+            "us_per_transform_eager": round(wall * 1e3, 2), "us_median_event_eager": round(med * 1e3, 2),
+            "us_per_transform_graph": round(gwall * 1e3, 2), "us_median_event_graph": round(gmed * 1e3, 2),
+            "transforms_per_s": 1e3 / min(wall, gwall)}
+
+
+def scan_row(phases, calls, alg_bytes):
+    """Time of the scan (tile reduce, carries, final sweeps) per call and its HBM fraction."""
+    ms = sum(phases.get(k, 0.0) for k in ("tiles_reduce", "carry", "tiles_final")) / calls
+    return {"ms": round(ms, 5), "alg_bytes": int(alg_bytes),
+            "hbm_frac": round(alg_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4) if ms > 0 else None}
+
+
+def bench_clustered(args, fgt, W, torch, np, dev):
+    """2^24 sources from a 64-component Gaussian mixture, 2^22 uniform targets, delta 1e-5."""
+    pr = W.clustered()
+    rows = []
+    for dt, name in ((torch.float64, "f64"), (torch.float32, "f32")):
+        esz = 8 if dt == torch.float64 else 4
+        p = fgt.plan(pr.delta, 6, dt)
+        X, Y, A = (torch.from_numpy(v).to(dev, dt) for v in (pr.x, pr.y, pr.alpha))
+        ws = fgt.workspace(p, pr.M, pr.N, dev)
+        u = torch.empty(pr.M, dtype=dt, device=dev)
+        fn = lambda: fgt.eval(X, Y, A, p, out=u, ws=ws)   # noqa: E731
+        wall, med = timed(fn, args.steps, args.warmup, torch)
+        fgt.profile_begin()
+        for _ in range(args.steps):
+            fn()
+        phases, calls = fgt.profile_end()
+        if fgt.last_device_status(ws) != fgt.FGT_OK:
+            raise RuntimeError("device status after the clustered workload")
+        P = pr.M + pr.N
+        rows.append({"dtype": name, "digits": 6, "n_modes": p.n_modes,
+                     "ms_per_transform": round(wall, 5), "ms_median_event": round(med, 5),
+                     "value": P * p.n_modes / (wall * 1e-3), "unit": "point-modes/s",
+                     "phase_ms": {k: round(v / calls, 5) for k, v in phases.items()},
+                     "scan": scan_row(phases, calls, 2 * esz * P + (esz + 4) * pr.M)})
+        del X, Y, A, ws, u
+    return {"workload": ("N = 2^24 sources from a 64-component Gaussian mixture (centres U[0,1), "
+                         "sigma log-uniform in [1e-5, 1e-2]), M = 2^22 targets U[0,1), "
+                         "alpha ~ U(-1,1), delta = 1e-5"),
+            "rows": rows}
+
+
+def bench_diff(args, fgt, W, torch, np, dev):
+    """M = N = 2^22, delta 1e-4: forward against forward + adjoint (all four gradients)."""
+    rows = []
+    for dt, name, digits in ((torch.float64, "f64", 9), (torch.float32, "f32", 4)):
+        pr, g = W.grad_problem(22, 1e-4, digits)
+        p = fgt.plan(pr.delta, digits, dt)
+        X, Y, A, G = (torch.from_numpy(v).to(dev, dt) for v in (pr.x, pr.y, pr.alpha, g))
+        ws = fgt.workspace(p, pr.M, pr.N, dev)
+        u = torch.empty(pr.M, dtype=dt, device=dev)
+
+        def fwd():
+            fgt.eval(X, Y, A, p, out=u, ws=ws)
+
+        def fwd_bwd():
+            fgt.eval(X, Y, A, p, out=u, ws=ws)
+            fgt.backward(X, Y, A, G, p, ws=ws, sorted=True)
+
+        wf, mf = timed(fwd, args.steps, args.warmup, torch)
+        wb, mb = timed(fwd_bwd, args.steps, args.warmup, torch)
+        if fgt.last_device_status(ws) != fgt.FGT_OK:
+            raise RuntimeError("device status after the differentiation workload")
+        P = pr.M + pr.N
+        rows.append({"dtype": name, "digits": digits, "n_modes": p.n_modes,
+                     "fwd_ms": round(wf, 5), "fwd_ms_median_event": round(mf, 5),
+                     "fwd_bwd_ms": round(wb, 5), "fwd_bwd_ms_median_event": round(mb, 5),
+                     "ratio": round(wb / wf, 4),
+                     "fwd_value": P * p.n_modes / (wf * 1e-3),
+                     "fwd_bwd_value": P * p.n_modes / (wb * 1e-3), "unit": "point-modes/s"})
+    return {"workload": ("M = N = 2^22 uniform on [0,1), alpha, g ~ N(0,1), delta = 1e-4, "
+                         "L = g . u; backward = dL/dalpha, dL/dx, dL/dy, dL/ddelta"),
+            "rows": rows}
 
 
 def main():
@@ -238,22 +445,27 @@ def main():
     ws = fgt.workspace(p, M, N, dev)
     u = torch.empty(M, dtype=dtype, device=dev)
 
-    for _ in range(args.warmup):
+    def step():
         fgt.eval(X, Y, A, p, out=u, ws=ws)
+
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
     status = fgt.last_device_status(ws)
     if status != fgt.FGT_OK:
         raise RuntimeError(f"device status {status} after warmup")
-
+    # An untimed profiled session first: the library then reuses its events and
+    # creates none while the timed calls are enqueued.
     fgt.profile_begin()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for _ in range(args.steps):
-        fgt.eval(X, Y, A, p, out=u, ws=ws)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+        step()
+    fgt.profile_end()
+
+    # Timed region: K steps bracketed by synchronisation; per-step HIP events on
+    # the current stream, and the library's phase events on the same stream.
+    fgt.profile_begin()
+    ms_step, ms_med = timed(step, args.steps, 0, torch)
     phases, calls = fgt.profile_end()
-    ms_step = (t1 - t0) * 1e3 / args.steps
 
     if args.copy_bytes > 0:
         src = torch.empty(args.copy_bytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
@@ -288,13 +500,14 @@ def main():
         sort_bytes = P * esz + N * esz + P * (2 * esz + 4)
     else:
         sort_bytes = (first + (n_run - 2) * middle + last) / n_run
-    scan_read = P * (2 * esz)                        # keys and strengths
+    scan_read = P * (2 * esz)                        # coordinates and strengths
     alg = {
         "k_onesweep": sort_bytes,
-        "k_final": scan_read + P * 4 + M * esz,      # + slots, + u scattered
+        "k_final": scan_read + P * 4 + M * esz,      # + ids, + u scattered
         "k_reduce": scan_read,
     }
     launches = {"k_onesweep": max(n_run, 1), "k_final": 1, "k_reduce": 1}
+    counter_name = {"k_onesweep": "k_onesweep", "k_final": "k_final_fast", "k_reduce": "k_reduce"}
 
     def roof(kernel):
         ms_launch = groups[kernel] / launches[kernel]
@@ -303,13 +516,14 @@ def main():
 
     dom = dominant if dominant in alg else "k_onesweep"
     gbs, ms_launch = roof(dom)
-    traffic = traffic_for(dom)
+    traffic = traffic_for(counter_name[dom])
     kernels = {}
     for k in ("k_onesweep", "k_reduce", "k_final"):
         g, ms = roof(k)
         kernels[k] = {"ms_per_launch": round(ms, 5), "launches_per_step": launches[k],
                       "alg_bytes_per_launch": int(alg[k]), "GBps": round(g, 1),
-                      "hbm_frac": round(g / HBM_PEAK_GBS, 4)}
+                      "hbm_frac": round(g / HBM_PEAK_GBS, 4),
+                      "valu_frac": valu_frac(counter_name[k], ms) if not args.fp32 else None}
     out = {
         "metric": METRIC,
         "value": P * n_modes / (ms_step * 1e-3),
@@ -318,6 +532,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 5),
+        "ms_median_event": round(ms_med, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -330,6 +545,7 @@ def main():
             "transforms_per_s": 1e3 / ms_step,
             "phase_ms_per_step": {k: round(v, 5) for k, v in per_step.items()},
             "kernels": kernels,
+            "scan": scan_row(phases, calls, P * 2 * esz + M * (esz + 4)),
         },
         "roofline": {
             "kernel": dom,
@@ -344,18 +560,15 @@ def main():
     }
     if not args.no_grad:
         G = torch.from_numpy(np.random.default_rng(5).standard_normal(M)).to(dev, dtype)
-        for _ in range(args.warmup):
+
+        def fwd_bwd():
             fgt.eval(X, Y, A, p, out=u, ws=ws)
             fgt.backward(X, Y, A, G, p, ws=ws, sorted=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            fgt.eval(X, Y, A, p, out=u, ws=ws)
-            fgt.backward(X, Y, A, G, p, ws=ws, sorted=True)
-        torch.cuda.synchronize()
-        ms_fb = (time.perf_counter() - t0) * 1e3 / args.steps
+
+        ms_fb, med_fb = timed(fwd_bwd, args.steps, args.warmup, torch)
         out["fwd_bwd"] = {
             "ms_per_step": round(ms_fb, 5),
+            "ms_median_event": round(med_fb, 5),
             "value": P * n_modes / (ms_fb * 1e-3),
             "unit": "point-modes/s",
             "ratio_to_fwd": round(ms_fb / ms_step, 4),
@@ -363,18 +576,21 @@ def main():
         }
     # plan reuse: new strengths on the sorted points
     A2 = torch.from_numpy(np.random.default_rng(6).standard_normal(N)).to(dev, dtype)
-    fgt.eval(X, Y, A, p, out=u, ws=ws)
-    for _ in range(args.warmup):
-        fgt.eval_sorted(A2, p, ws, M, out=u)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        fgt.eval_sorted(A2, p, ws, M, out=u)
-    torch.cuda.synchronize()
-    ms_reuse = (time.perf_counter() - t0) * 1e3 / args.steps
-    out["plan_reuse"] = {"ms_per_step": round(ms_reuse, 5),
+    step()
+    ms_reuse, med_reuse = timed(lambda: fgt.eval_sorted(A2, p, ws, M, out=u), args.steps,
+                                args.warmup, torch)
+    out["plan_reuse"] = {"ms_per_step": round(ms_reuse, 5), "ms_median_event": round(med_reuse, 5),
                          "value": P * n_modes / (ms_reuse * 1e-3), "unit": "point-modes/s",
                          "step": "fgt_eval_sorted: strengths gathered into the kept sort, then the scans"}
+    if fgt.last_device_status(ws) != fgt.FGT_OK:
+        raise RuntimeError("device status after the headline workload")
+    del ws
+    if not args.no_small and not args.fp32:
+        out["small"] = bench_small(args, fgt, W, torch, np, dev)
+    if not args.no_clustered and not args.fp32:
+        out["clustered"] = bench_clustered(args, fgt, W, torch, np, dev)
+    if not args.no_diff and not args.fp32:
+        out["differentiation"] = bench_diff(args, fgt, W, torch, np, dev)
     if not args.no_identical and not args.fp32:
         out["identical_points"] = bench_identical(args, fgt, W, torch, np, dev)
     if not args.no_batched and not args.fp32:

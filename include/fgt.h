@@ -135,6 +135,40 @@ int fgt_eval(fgt_plan_t plan, const void* x, int64_t M, const void* y, const voi
 int fgt_eval_self(fgt_plan_t plan, const void* x, int64_t N, const void* alpha, void* u, int flags,
                   void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Flag for fgt_sort: sort every key bit, and code FP64 keys only where exact. */
+#define FGT_SORT_EXACT 4
+
+/*
+ * fgt_sort -- the sort step of Section 4 alone, exactly as fgt_eval runs it:
+ * the merged points [y_1..y_N, x_1..x_M] in ascending order (the paper sorts
+ * sources and targets before the recurrences and times that step on its
+ * own, Section 5).  Writes, per sorted position p, the merged index perm[p]
+ * (perm[p] < N: source perm[p]; otherwise target perm[p] - N) and the
+ * coordinate z[p] that the scans use; either may be null.  alpha (may be
+ * null) is gathered into sorted order as fgt_eval does, so with alpha given
+ * the workspace afterwards holds the state fgt_eval_sorted and fgt_backward
+ * (FGT_SORTED) start from.
+ *   flags 0: the plan's resolution.  Points whose coordinates differ by less
+ *          than the key width resolution[0] may be left in either order (the
+ *          change this makes to any transform value is at most 1e-6 E_n
+ *          sum|alpha|), and an FP64 coordinate may be moved by less than
+ *          resolution[1] when it is finer than the key grid fitted to the
+ *          range (0 when every point lies on that grid).
+ *   FGT_SORT_EXACT: every key bit is sorted and the FP64 grid code is used
+ *          only where it is exact: perm is then the stable ascending order of
+ *          [y; x] (equal coordinates keep their merged order, -0 equals +0)
+ *          and z[p] is the input coordinate bit for bit (-0 stored as +0).
+ *   perm       [M + N] uint32 device array, z [M + N] of the plan's type.
+ *   resolution host double[2] (may be null): the key width and the FP64
+ *              code tolerance of this call (both 0 with FGT_SORT_EXACT).
+ *   ws         as for fgt_eval.
+ * Non-finite coordinates are reported by fgt_last_device_status.
+ * Errors: as fgt_eval, plus FGT_EINVAL for unknown flags.
+ */
+int fgt_sort(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha, int64_t N,
+             int flags, uint32_t* perm, void* z, double* resolution, void* ws, size_t ws_bytes,
+             hipStream_t stream);
+
 /*
  * fgt_eval_sorted -- fgt_eval for new strengths alpha[N] on points already
  * sorted: `ws` must hold the sorted state that the last fgt_eval (or

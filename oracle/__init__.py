@@ -72,6 +72,8 @@ def _load():
                                                dp, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int]
         lib.oracle_soe_deriv_brute.restype = ctypes.c_int
         lib.oracle_max_threads.restype = ctypes.c_int
+        lib.oracle_last_sort_seconds.argtypes = []
+        lib.oracle_last_sort_seconds.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -86,6 +88,11 @@ def _ptr(a: np.ndarray):
 
 def max_threads() -> int:
     return int(_load().oracle_max_threads())
+
+
+def last_sort_seconds() -> float:
+    """Wall time of the sort inside the last soe_recurrence call (timing only)."""
+    return float(_load().oracle_last_sort_seconds())
 
 
 def direct(x, y, alpha, delta: float, cutoff: float = DEFAULT_CUTOFF, threads: int = 0,

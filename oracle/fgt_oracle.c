@@ -195,14 +195,20 @@ int oracle_direct(const double* x, int64_t K, const double* y, const double* alp
  * itself counts with h+ (sign +1), as the sweeps order it.
  * plant 7 (deriv only): the h- rows keep the sign of the h+ rows.
  * ---------------------------------------------------------------------- */
+/* Wall time of the last O2 call's sort (benchmark use only; no effect on results). */
+static double g_last_sort_seconds = 0.0;
+double oracle_last_sort_seconds(void) { return g_last_sort_seconds; }
+
 int oracle_soe_recurrence_field(const double* x, int64_t M, const double* y, const double* alpha,
                                 int64_t N, double delta, int n_modes, const double* tau_re,
                                 const double* tau_im, const double* om_re, const double* om_im,
                                 int deriv, double* u, int nthreads, int plant) {
   if (M < 0 || N < 0 || n_modes < 0 || !(delta > 0)) return 1;
   if (M == 0) return 0;
+  const double t_sort0 = omp_get_wtime();
   vi_t* xs = sorted_copy(x, M);
   vi_t* ys = sorted_copy(y, N);
+  g_last_sort_seconds = omp_get_wtime() - t_sort0;
   double* beta = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
   const int64_t rows = 2 * (int64_t)n_modes;
   double* part = (double*)calloc((size_t)(rows > 0 ? rows : 1) * (size_t)M, sizeof(double));

@@ -16,6 +16,7 @@ FGT_F64, FGT_F32 = 0, 1
 FGT_MAX_MODES = 8
 FGT_SORTED = 1
 FGT_PRESORTED = 2
+FGT_SORT_EXACT = 4
 
 _lib = None
 
@@ -47,6 +48,8 @@ def load() -> ctypes.CDLL:
     lib.fgt_workspace_size.restype = ctypes.c_size_t
     lib.fgt_eval.argtypes = [vp, vp, c_i64, vp, vp, c_i64, vp, vp, ctypes.c_size_t, vp]
     lib.fgt_eval.restype = c_int
+    lib.fgt_sort.argtypes = [vp, vp, c_i64, vp, vp, c_i64, c_int, vp, vp, dp, vp, ctypes.c_size_t, vp]
+    lib.fgt_sort.restype = c_int
     lib.fgt_eval_sorted.argtypes = [vp, c_i64, c_i64, vp, vp, vp, ctypes.c_size_t, vp]
     lib.fgt_eval_sorted.restype = c_int
     lib.fgt_eval_self.argtypes = [vp, vp, c_i64, vp, vp, c_int, vp, ctypes.c_size_t, vp]

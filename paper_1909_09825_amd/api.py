@@ -164,6 +164,47 @@ def eval_self(x: torch.Tensor, alpha: torch.Tensor, p: Plan, presorted: bool = F
     return out
 
 
+def sort(x: torch.Tensor, y: torch.Tensor, p: Plan, alpha: torch.Tensor | None = None,
+         exact: bool = False, ws: torch.Tensor | None = None):
+    """The sort step alone (fgt_sort): (perm, z, (key_width, code_tol)).
+
+    perm[p] is the merged index of sorted position p (< N: source, else target
+    perm[p] - N) as an int64 tensor, z the sorted coordinates the scans use.
+    exact=True sorts every key bit and keeps FP64 coordinates exact, so perm
+    is the stable ascending order of [y; x].
+    """
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise ValueError("x must be a CUDA (HIP) tensor")
+    dev = x.device
+    x = _vec(x, "x", p.dtype, dev)
+    y = _vec(y, "y", p.dtype, dev)
+    if alpha is not None:
+        alpha = _vec(alpha, "alpha", p.dtype, dev)
+        if alpha.shape[0] != y.shape[0]:
+            raise ValueError("y and alpha must have the same length")
+    M, N = x.shape[0], y.shape[0]
+    if ws is None:
+        ws = workspace(p, M, N, dev)
+    need = _check_ws(p, ws, M, N, dev)
+    perm = torch.empty(M + N, dtype=torch.int32, device=dev)
+    z = torch.empty(M + N, dtype=p.dtype, device=dev)
+    res = (ctypes.c_double * 2)()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    check(p._lib.fgt_sort(p.handle, x.data_ptr(), M, y.data_ptr(),
+                          alpha.data_ptr() if alpha is not None else None, N,
+                          _lib.FGT_SORT_EXACT if exact else 0, perm.data_ptr(), z.data_ptr(), res,
+                          ws.data_ptr(), need, stream), "fgt_sort")
+    return perm.long() & 0xFFFFFFFF, z, (res[0], res[1])
+
+
+def sort_resolution(p: Plan) -> tuple[float, float]:
+    """(key width, FP64 code tolerance) that the plan's sort uses (host query, no device work)."""
+    res = (ctypes.c_double * 2)()
+    check(p._lib.fgt_sort(p.handle, None, 0, None, None, 0, 0, None, None, res, None, 0, None),
+          "fgt_sort")
+    return res[0], res[1]
+
+
 def eval_sorted(alpha: torch.Tensor, p: Plan, ws: torch.Tensor, M: int,
                 out: torch.Tensor | None = None) -> torch.Tensor:
     """u for new strengths on the points whose sort `ws` holds (from eval or backward).

@@ -181,6 +181,17 @@ struct Profiler {
     bool f64;
   };
   std::vector<Call> calls;
+  // Events of earlier sessions, reused so that a session after the first
+  // creates none while the calls it times are being enqueued.
+  std::vector<hipEvent_t> pool;
+  hipError_t take(hipEvent_t* ev) {
+    if (!pool.empty()) {
+      *ev = pool.back();
+      pool.pop_back();
+      return hipSuccess;
+    }
+    return hipEventCreate(ev);
+  }
 };
 static Profiler g_prof;
 
@@ -228,6 +239,45 @@ hipError_t backward(const fgt_plan_s* plan, const Workspace& w, const void* x, i
   }
   return adjoint_points<T>(w, plan->modes, M, N, (const T*)g, (T*)dx, (T*)dalpha, (T*)dy,
                            (T*)ddelta, plan->delta, s);
+}
+
+// Validation and launch of fgt_eval on a given workspace; `profile` records
+// the phase events of fgt_profile_begin.
+int eval_entry(const fgt_plan_s* plan, const void* x, int64_t M, const void* y, const void* alpha,
+               int64_t N, void* u, void* ws, size_t ws_bytes, hipStream_t stream, bool profile) {
+  if (!plan || M < 0 || N < 0) return FGT_EINVAL;
+  if (M + N >= (int64_t(1) << 32)) return FGT_EINVAL;
+  if (M == 0) return FGT_OK;
+  if (!x || !u) return FGT_EINVAL;
+  const bool f64 = plan->dtype == FGT_F64;
+  if (N == 0) {
+    hipError_t e = f64 ? fill_zero<double>((double*)u, M, stream)
+                       : fill_zero<float>((float*)u, M, stream);
+    return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+  }
+  if (!y || !alpha || !ws) return FGT_EINVAL;
+  if (((uintptr_t)ws & 255u) != 0) return FGT_EINVAL;
+  const int esz = f64 ? 8 : 4;
+  const Workspace w = layout(ws, M + N, esz, plan->modes.n);
+  if (ws_bytes < w.total) return FGT_EINVAL;
+  Timeline tl;
+  Profiler::Call call;
+  if (profile) {
+    call.n = 0;
+    call.f64 = f64;
+    for (int i = 0; i <= kMaxPhases; ++i) {
+      if (g_prof.take(&call.ev[i]) != hipSuccess) return FGT_EDEVICE;
+    }
+    tl.ev = call.ev;
+    tl.cap = kMaxPhases + 1;
+  }
+  hipError_t e = f64 ? forward<double>(plan, w, x, M, y, alpha, N, u, true, stream, &tl)
+                     : forward<float>(plan, w, x, M, y, alpha, N, u, true, stream, &tl);
+  if (profile) {
+    call.n = tl.n;
+    g_prof.calls.push_back(call);
+  }
+  return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
 }
 
 }  // namespace
@@ -301,37 +351,38 @@ size_t fgt_workspace_size(fgt_plan_t plan, int64_t M, int64_t N) {
 
 int fgt_eval(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha,
              int64_t N, void* u, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return fgt::eval_entry(plan, x, M, y, alpha, N, u, ws, ws_bytes, stream, fgt::g_prof.on);
+}
+
+int fgt_sort(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha, int64_t N,
+             int flags, uint32_t* perm, void* z, double* resolution, void* ws, size_t ws_bytes,
+             hipStream_t stream) {
   if (!plan || M < 0 || N < 0) return FGT_EINVAL;
   if (M + N >= (int64_t(1) << 32)) return FGT_EINVAL;
-  if (M == 0) return FGT_OK;
-  if (!x || !u) return FGT_EINVAL;
-  const bool f64 = plan->dtype == FGT_F64;
-  if (N == 0) {
-    hipError_t e = f64 ? fgt::fill_zero<double>((double*)u, M, stream)
-                       : fgt::fill_zero<float>((float*)u, M, stream);
-    return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+  if (flags & ~FGT_SORT_EXACT) return FGT_EINVAL;
+  const bool exact = (flags & FGT_SORT_EXACT) != 0;
+  const fgt::SortRes res = exact ? fgt::SortRes{0.0, 0.0, 0.0} : plan->modes.sort;
+  if (resolution) {
+    resolution[0] = res.key_width;
+    resolution[1] = res.code_tol;
   }
-  if (!y || !alpha || !ws) return FGT_EINVAL;
+  const int64_t P = M + N;
+  if (P == 0) return FGT_OK;
+  if ((M > 0 && !x) || (N > 0 && !y) || !ws) return FGT_EINVAL;
   if (((uintptr_t)ws & 255u) != 0) return FGT_EINVAL;
-  const int esz = f64 ? 8 : 4;
-  const fgt::Workspace w = fgt::layout(ws, M + N, esz, plan->modes.n);
+  const bool f64 = plan->dtype == FGT_F64;
+  const fgt::Workspace w = fgt::layout(ws, P, f64 ? 8 : 4, plan->modes.n);
   if (ws_bytes < w.total) return FGT_EINVAL;
-  fgt::Timeline tl;
-  fgt::Profiler::Call call;
-  if (fgt::g_prof.on) {
-    call.n = 0;
-    call.f64 = f64;
-    for (int i = 0; i <= fgt::kMaxPhases; ++i) {
-      if (hipEventCreate(&call.ev[i]) != hipSuccess) return FGT_EDEVICE;
-    }
-    tl.ev = call.ev;
-    tl.cap = fgt::kMaxPhases + 1;
-  }
-  hipError_t e = f64 ? fgt::forward<double>(plan, w, x, M, y, alpha, N, u, true, stream, &tl)
-                     : fgt::forward<float>(plan, w, x, M, y, alpha, N, u, true, stream, &tl);
-  if (fgt::g_prof.on) {
-    call.n = tl.n;
-    fgt::g_prof.calls.push_back(call);
+  fgt::Timeline none;
+  hipError_t e;
+  if (f64) {
+    e = fgt::sort_points<double>(w, (const double*)x, M, (const double*)y, (const double*)alpha, N,
+                                 res, stream, &none);
+    if (e == hipSuccess && (perm || z)) e = fgt::copy_sorted<double>(w, P, perm, (double*)z, stream);
+  } else {
+    e = fgt::sort_points<float>(w, (const float*)x, M, (const float*)y, (const float*)alpha, N, res,
+                                stream, &none);
+    if (e == hipSuccess && (perm || z)) e = fgt::copy_sorted<float>(w, P, perm, (float*)z, stream);
   }
   return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
 }
@@ -835,7 +886,7 @@ int fgt_profile_end(double* ms, int max_phases, int* n_phases, int* n_calls) {
       acc[name] += t;
       if (name + 1 > phases) phases = name + 1;
     }
-    for (int i = 0; i <= fgt::kMaxPhases; ++i) (void)hipEventDestroy(c.ev[i]);
+    for (int i = 0; i <= fgt::kMaxPhases; ++i) fgt::g_prof.pool.push_back(c.ev[i]);
   }
   if (n_calls) *n_calls = (int)fgt::g_prof.calls.size();
   fgt::g_prof.calls.clear();

@@ -344,6 +344,9 @@ hipError_t gather_strengths(const Workspace& w, int64_t P, uint32_t lo, uint32_t
 template <class T>
 hipError_t adjoint_points(const Workspace& w, const Modes& md, int64_t M, int64_t N, const T* g,
                           T* dx, T* dalpha, T* dy, T* ddelta, double delta, hipStream_t s);
+// Copy the sorted state (merged ids, sorted coordinates) to caller arrays (either may be null).
+template <class T>
+hipError_t copy_sorted(const Workspace& w, int64_t P, uint32_t* perm, T* z, hipStream_t s);
 template <class T>
 hipError_t fill_zero(T* u, int64_t n, hipStream_t s);
 // Points given in ascending order: coordinates and identity ids written as the sort

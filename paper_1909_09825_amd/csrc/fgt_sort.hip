@@ -621,7 +621,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     const uint32_t out = outpos[r];
     const uint32_t id = sid[j];
     if (last) {
-      b_out[out] = (int64_t)id < N ? alpha[id] : T(0);
+      b_out[out] = (alpha && (int64_t)id < N) ? alpha[id] : T(0);
       ids_out[out] = id;
     } else {
       iout[out] = id;
@@ -654,6 +654,22 @@ __global__ __launch_bounds__(256) void k_presorted(const T* __restrict__ x, int6
   }
 }
 
+// The sorted state left by the last sort: merged index and coordinate of every
+// sorted position (either output may be null).
+template <class T>
+__global__ __launch_bounds__(256) void k_copy_sorted(const void* keys0, const void* keys1,
+                                                     const PassInfo* __restrict__ pass,
+                                                     const uint32_t* __restrict__ ids, int64_t P,
+                                                     uint32_t* __restrict__ perm,
+                                                     T* __restrict__ z) {
+  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += stride) {
+    if (perm) perm[p] = ids[p];
+    if (z) z[p] = keys(p);
+  }
+}
+
 }  // namespace
 
 template <class T>
@@ -668,6 +684,18 @@ hipError_t presorted_points(const Workspace& w, const T* x, const T* alpha, int6
                      w.ids, w.pass, w.status);
   return hipGetLastError();
 }
+
+template <class T>
+hipError_t copy_sorted(const Workspace& w, int64_t P, uint32_t* perm, T* z, hipStream_t s) {
+  int64_t blocks = (P + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_copy_sorted<T>, dim3((unsigned)blocks), dim3(256), 0, s, w.keys[0], w.keys[1],
+                     w.pass, w.ids, P, perm, z);
+  return hipGetLastError();
+}
+template hipError_t copy_sorted<double>(const Workspace&, int64_t, uint32_t*, double*, hipStream_t);
+template hipError_t copy_sorted<float>(const Workspace&, int64_t, uint32_t*, float*, hipStream_t);
 
 template hipError_t presorted_points<double>(const Workspace&, const double*, const double*,
                                              int64_t, hipStream_t);

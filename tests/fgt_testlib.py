@@ -51,6 +51,17 @@ def oracle_Eprime(p) -> float:
     return float(OTABLES[p.n_modes]["Eprime"])
 
 
+def oracle_sum_omega(p) -> float:
+    """sum_k |omega_k| of the oracle's table with the plan's mode count."""
+    return float(np.sum(np.abs(OTABLES[p.n_modes]["omega"])))
+
+
+def oracle_sum_dom(p) -> float:
+    """sum_k |tau_k omega_k| (tau_k = tau0_k / sqrt(delta)) of the oracle's table."""
+    t = OTABLES[p.n_modes]
+    return float(np.sum(np.abs(t["tau0"] * t["omega"]))) / math.sqrt(p.delta)
+
+
 def impl_tol(alpha, p, P, eps=EPS64):
     """Tolerance for GPU vs the oracle's SOE recurrence (same table, different
     summation order): each of the ~2 log2(P) levels of the scan and the
@@ -59,7 +70,7 @@ def impl_tol(alpha, p, P, eps=EPS64):
     leave points closer than its key resolution unordered, which it bounds by
     1e-6 E_n sum|alpha|."""
     s_alpha = float(np.sum(np.abs(alpha)))
-    s_omega = float(np.sum(np.abs(p.omega)))
+    s_omega = oracle_sum_omega(p)
     return (64.0 * eps * s_alpha * s_omega * max(1.0, math.log2(max(P, 2)))
             + 1e-6 * oracle_E(p) * s_alpha)
 

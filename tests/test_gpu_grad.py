@@ -21,7 +21,8 @@ import torch
 import oracle
 import paper_1909_09825_amd as fgt
 from paper_1909_09825_amd import workloads as W
-from fgt_testlib import EPS32, EPS64, impl_tol, oracle_E, oracle_Eprime, oracle_table, say, to_dev
+from fgt_testlib import (EPS32, EPS64, impl_tol, oracle_E, oracle_Eprime, oracle_sum_dom, oracle_table,
+                         say, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +30,7 @@ pytestmark = pytest.mark.gpu
 def impl_tol_der(w, p, P, eps=EPS64):
     """Rounding tolerance of a derivative field: impl_tol with |tau_k omega_k| in place of |omega_k|."""
     s_w = float(np.sum(np.abs(w)))
-    s_dom = float(np.sum(np.abs(p.tau * p.omega)))
+    s_dom = oracle_sum_dom(p)
     tie = 2.0 * oracle_Eprime(p) / math.sqrt(p.delta) * 1e-6 * s_w
     return 64.0 * eps * s_w * s_dom * max(1.0, math.log2(max(P, 2))) + tie
 

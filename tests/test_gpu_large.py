@@ -17,7 +17,8 @@ import torch
 import oracle
 import paper_1909_09825_amd as fgt
 from paper_1909_09825_amd import workloads as W
-from fgt_testlib import EPS32, check_direct, gpu_eval, impl_tol, oracle_E, oracle_table, say
+from fgt_testlib import (EPS32, check_direct, gpu_eval, impl_tol, oracle_E, oracle_sum_omega,
+                         oracle_table, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -105,7 +106,31 @@ def test_clustered_fp32(digits):
     err = float(np.max(np.abs(u[idx] - ref))) / s_alpha
     ref64 = oracle.direct(pr.x[idx], pr.y, pr.alpha, pr.delta)
     err64 = float(np.max(np.abs(u[idx] - ref64))) / float(np.sum(np.abs(pr.alpha)))
-    bound = oracle_E(p) + 64 * EPS32 * float(np.sum(np.abs(p.omega)))
+    bound = oracle_E(p) + 64 * EPS32 * oracle_sum_omega(p)
     say(f"   FP32 error / sum|alpha| = {err:.3e} vs rounded inputs, {err64:.3e} vs FP64 inputs "
         f"(E = {oracle_E(p):.2e}, bound {bound:.2e})")
     assert err <= bound
+
+
+def test_plan_reuse_full_size():
+    """fgt_eval_sorted (the sort kept, new strengths) at 2^24 + 2^24, delta 1e-4,
+    6 digits -- the launch the benchmark's plan-reuse line times -- against O1 on
+    sampled targets and O2 on every target, for strengths the sort never saw."""
+    pr = large(1e-4)
+    p = fgt.plan(1e-4, 6)
+    X, Y, A = (torch.from_numpy(v).to("cuda") for v in (pr.x, pr.y, pr.alpha))
+    ws = fgt.workspace(p, pr.M, pr.N, X.device)
+    say("[gpu] fgt_eval then fgt_eval_sorted with new alpha, 2^24 + 2^24")
+    fgt.eval(X, Y, A, p, ws=ws)
+    a2 = W.rng(2, 50).standard_normal(pr.N)
+    u = fgt.eval_sorted(torch.from_numpy(a2).to("cuda"), p, ws, pr.M).cpu().numpy()
+    assert fgt.last_device_status(ws) == fgt.FGT_OK
+    idx = W.sample_indices(pr.M, 2048, cfg=2, sub=50)
+    e1, _ = check_direct(u[idx], pr.x[idx], pr.y, a2, 1e-4, p)
+    assert e1 <= 2 * oracle_E(p)
+    t = oracle_table(p)
+    u2 = oracle.soe_recurrence(pr.x, pr.y, a2, 1e-4, t["tau0"], t["omega"])
+    e2 = float(np.max(np.abs(u - u2)))
+    tol = impl_tol(a2, p, pr.M + pr.N)
+    say(f"   O2 check (all {pr.M} targets): {e2:.3e} (tol {tol:.3e})")
+    assert e2 <= tol

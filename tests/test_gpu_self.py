@@ -95,3 +95,21 @@ def test_self_empty():
     x = torch.empty(0, dtype=torch.float64, device="cuda")
     u = fgt.eval_self(x, x, p)
     assert u.shape == (0,)
+
+
+@pytest.mark.parametrize("delta,digits", [(1.0, 6), (1e-4, 6)])
+def test_self_full_size(delta, digits):
+    """N = 10^7 (the Table 1 size; 77 chunks of 64 scan tiles, so the carries
+    cross chunks): O1 on sampled points, O2 on every point."""
+    x, a = W.identical_uniform(10_000_000)
+    u, p, st = run_self(x, a, delta, digits, case="10^7")
+    assert st == fgt.FGT_OK
+    idx = W.sample_indices(len(x), 256 if delta == 1.0 else 2048, cfg=6, sub=digits)
+    ref = oracle.direct(x[idx], x, a, delta)
+    e1 = float(np.max(np.abs(u[idx] - ref))) / float(np.abs(a).sum())
+    t = oracle_table(p)
+    ref2 = oracle.soe_recurrence(x, x, a, delta, t["tau0"], t["omega"])
+    e2 = float(np.max(np.abs(u - ref2)))
+    tol = impl_tol(a, p, len(x))
+    say(f"   O1 err / sum|alpha| = {e1:.3e} (2E = {2 * oracle_E(p):.3e}); O2 err {e2:.3e} (tol {tol:.3e})")
+    assert e1 <= 2 * oracle_E(p) and e2 <= tol

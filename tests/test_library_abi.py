@@ -200,3 +200,35 @@ def test_batch_workspace_size_grows_with_points_and_columns():
     assert 0 < s1 < s16 < big
     assert lib.fgt_eval_batched_workspace_size(3, _i64p(xo), _i64p(yo), 0, 6) == 0
     assert lib.fgt_eval_batched_workspace_size(3, _i64p(xo), _i64p(yo), 4, 0) == 0
+
+
+@pytest.mark.parametrize("digits", [3, 4, 6, 9, 11])
+@pytest.mark.parametrize("delta", [1e-6, 1e-3, 1.0])
+def test_sort_resolution_from_oracle_table(delta, digits, otables):
+    """The key width the sort may leave unordered, pinned by the oracle's table:
+    a source and a target at scaled distance s that swap places change a value
+    by exactly |Re sum_k omega_k (e^{tau0_k s} - e^{-tau0_k s})| per unit strength
+    (S evaluated at -s instead of s); at s = width / sqrt(delta) this must stay
+    within 1e-6 E_n (and not be pointlessly small).  The FP64 code tolerance c
+    moves each end of a pair by < c, changing a term by at most
+    (max|G'| + E'_n) 2 c / sqrt(delta) per unit strength, which must stay within
+    0.5e-6 E_n."""
+    p = fgt.plan(delta, digits)
+    kw, ctol = fgt.sort_resolution(p)
+    t = otables[p.n_modes]
+    E, Ep = float(t["E"]), float(t["Eprime"])
+    s = kw / np.sqrt(delta)
+    swap = abs(float(np.sum(t["omega"] * 2.0 * np.sinh(t["tau0"] * s)).real))   # no cancellation
+    assert 0.5e-6 * E <= swap <= 1.002e-6 * E
+    r = np.linspace(0.0, 10.0, 200001)
+    max_dg = float(np.max(np.abs(0.5 * r * np.exp(-r * r / 4))))
+    shift = (max_dg + Ep) * 2 * ctol / np.sqrt(delta)
+    assert 0.2e-6 * E <= shift <= 0.5e-6 * E * 1.002
+    # exact mode reports zero widths; unknown flags are refused
+    res = (ctypes.c_double * 2)()
+    lib = _lib.load()
+    assert lib.fgt_sort(p.handle, None, 0, None, None, 0, _lib.FGT_SORT_EXACT, None, None, res,
+                        None, 0, None) == _lib.FGT_OK
+    assert res[0] == 0.0 and res[1] == 0.0
+    assert lib.fgt_sort(p.handle, None, 0, None, None, 0, 8, None, None, res, None, 0,
+                        None) == _lib.FGT_EINVAL
