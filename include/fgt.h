@@ -44,6 +44,7 @@ extern "C" {
 #define FGT_ENONFINITE 3    /* a coordinate was NaN or infinite (reported by fgt_last_device_status) */
 #define FGT_EDEVICE 4       /* a HIP runtime call failed */
 #define FGT_EUNSORTED 5     /* FGT_PRESORTED given for points that are not in ascending order */
+#define FGT_ENOSPACE 6      /* problem larger than the fixed workspace of fgt_eval_noalloc */
 
 /* Element types. */
 #define FGT_F64 0
@@ -114,6 +115,31 @@ size_t fgt_workspace_size(fgt_plan_t plan, int64_t M, int64_t N);
  */
 int fgt_eval(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha,
              int64_t N, void* u, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * fgt_eval_noalloc -- fgt_eval for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and result as fgt_eval, without the workspace:
+ * the call uses a fixed array of FGT_NOALLOC_BYTES bytes in device memory,
+ * built into the library, one per device, held until the process ends.  It
+ * calls no allocator (neither hipMalloc nor any library routine that
+ * allocates).  The address of a device's array is looked up once, at the
+ * first call on that device (then a mutex serialises the look-up).
+ *   stream  must belong to the current device (FGT_EINVAL otherwise).
+ * Limit: fgt_workspace_size(plan, M, N) <= FGT_NOALLOC_BYTES, which holds for
+ * M + N up to 1,500,000 points (FP64 or FP32, any digits); larger problems
+ * return FGT_ENOSPACE and enqueue nothing.
+ * Every call on one device shares that device's array: the call clears what
+ * must start at zero, and two calls that overlap in time on one device (other
+ * streams, other host threads) race and give wrong results.  Calls on one
+ * stream are ordered and safe.  The array's device status word is not
+ * readable (fgt_last_device_status needs a caller's workspace): with
+ * non-finite coordinates u is unspecified.
+ * Errors: as fgt_eval, plus FGT_ENOSPACE.
+ */
+#define FGT_NOALLOC_BYTES (64u << 20)
+int fgt_eval_noalloc(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha,
+                     int64_t N, void* u, hipStream_t stream);
 
 /* Flag for fgt_backward: the workspace already holds the sort of (x, y). */
 #define FGT_SORTED 1

@@ -6,13 +6,13 @@ sort of targets and sources, then forward and backward complex recurrences
 per mode as parallel scans, all in hand-written HIP kernels behind the C ABI
 of include/fgt.h.
 """
-from ._lib import (FGT_EDEVICE, FGT_EINVAL, FGT_ENONFINITE, FGT_EUNSORTED, FGT_EUNSUPPORTED,
+from ._lib import (FGT_EDEVICE, FGT_EINVAL, FGT_ENONFINITE, FGT_ENOSPACE, FGT_NOALLOC_BYTES, FGT_EUNSORTED, FGT_EUNSUPPORTED,
                    FGT_F32, FGT_F64, FGT_OK, FGT_PRESORTED, FGT_SORT_EXACT, FGT_SORTED, FGTError, LIB_PATH)
 from .api import (BatchPlan, GaussTransform, Plan, backward, batch_plan, batch_workspace, eval,
-                  eval_batch, eval_self, sort, sort_resolution, eval_sorted, gauss_transform, last_device_status, max_digits, plan,
+                  eval_batch, eval_noalloc, eval_self, sort, sort_resolution, eval_sorted, gauss_transform, last_device_status, max_digits, plan,
                   profile_begin, profile_end, workspace)
 
-__all__ = ["Plan", "plan", "eval", "sort", "sort_resolution", "FGT_SORT_EXACT", "eval_self", "eval_sorted", "backward", "GaussTransform", "gauss_transform",
+__all__ = ["Plan", "plan", "eval", "eval_noalloc", "sort", "sort_resolution", "FGT_SORT_EXACT", "FGT_ENOSPACE", "FGT_NOALLOC_BYTES", "eval_self", "eval_sorted", "backward", "GaussTransform", "gauss_transform",
            "BatchPlan", "batch_plan", "eval_batch", "batch_workspace",
            "workspace", "last_device_status", "max_digits", "FGTError",
            "FGT_OK", "FGT_EINVAL", "FGT_EUNSUPPORTED", "FGT_ENONFINITE", "FGT_EDEVICE",

@@ -12,6 +12,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libfgt.so")
 
 FGT_OK, FGT_EINVAL, FGT_EUNSUPPORTED, FGT_ENONFINITE, FGT_EDEVICE, FGT_EUNSORTED = 0, 1, 2, 3, 4, 5
+FGT_ENOSPACE = 6
+FGT_NOALLOC_BYTES = 64 << 20
 FGT_F64, FGT_F32 = 0, 1
 FGT_MAX_MODES = 8
 FGT_SORTED = 1
@@ -48,6 +50,8 @@ def load() -> ctypes.CDLL:
     lib.fgt_workspace_size.restype = ctypes.c_size_t
     lib.fgt_eval.argtypes = [vp, vp, c_i64, vp, vp, c_i64, vp, vp, ctypes.c_size_t, vp]
     lib.fgt_eval.restype = c_int
+    lib.fgt_eval_noalloc.argtypes = [vp, vp, c_i64, vp, vp, c_i64, vp, vp]
+    lib.fgt_eval_noalloc.restype = c_int
     lib.fgt_sort.argtypes = [vp, vp, c_i64, vp, vp, c_i64, c_int, vp, vp, dp, vp, ctypes.c_size_t, vp]
     lib.fgt_sort.restype = c_int
     lib.fgt_eval_sorted.argtypes = [vp, c_i64, c_i64, vp, vp, vp, ctypes.c_size_t, vp]

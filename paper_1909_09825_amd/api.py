@@ -125,6 +125,31 @@ def eval(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor, p: Plan,
     return out
 
 
+def eval_noalloc(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor, p: Plan,
+                 out: torch.Tensor) -> torch.Tensor:
+    """eval() into `out` with the library's fixed per-device workspace (fgt_eval_noalloc).
+
+    Nothing is allocated, here or in the library, so the call may run where
+    allocation is not allowed (e.g. under graph capture).  Problems whose
+    workspace exceeds FGT_NOALLOC_BYTES raise FGTError(FGT_ENOSPACE); calls that
+    overlap in time on one device race on the shared workspace.
+    """
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise ValueError("x must be a CUDA (HIP) tensor")
+    dev = x.device
+    for t, name in ((x, "x"), (y, "y"), (alpha, "alpha"), (out, "out")):
+        if (not isinstance(t, torch.Tensor) or t.dim() != 1 or t.dtype != p.dtype
+                or t.device != dev or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous 1-D {p.dtype} tensor on {dev}")
+    M, N = x.shape[0], y.shape[0]
+    if alpha.shape[0] != N or out.shape[0] != M:
+        raise ValueError("alpha must have length N and out length M")
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    check(p._lib.fgt_eval_noalloc(p.handle, x.data_ptr(), M, y.data_ptr(), alpha.data_ptr(), N,
+                                  out.data_ptr(), stream), "fgt_eval_noalloc")
+    return out
+
+
 def _check_ws(p: Plan, ws: torch.Tensor, M: int, N: int, dev) -> int:
     need = p.workspace_size(M, N)
     if (not isinstance(ws, torch.Tensor) or ws.numel() * ws.element_size() < need

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -280,6 +281,36 @@ int eval_entry(const fgt_plan_s* plan, const void* x, int64_t M, const void* y, 
   return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
 }
 
+// Workspace of fgt_eval_noalloc: a fixed device array, one copy per device,
+// held until the process ends.  Host code never uses the array's name as a
+// device address: the address of each device's copy is taken once, with that
+// device current, and kept in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[FGT_NOALLOC_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+// The scratch array of the device that `stream` belongs to (the current
+// device for the null stream), which must be the current device.
+int scratch_of_stream(hipStream_t stream, void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return FGT_EDEVICE;
+  if (stream) {
+    hipDevice_t sdev = -1;
+    if (hipStreamGetDevice(stream, &sdev) != hipSuccess) return FGT_EDEVICE;
+    if (sdev != dev) return FGT_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FGT_EDEVICE;
+    if (((uintptr_t)p & 255u) != 0) return FGT_EDEVICE;
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return FGT_OK;
+}
+
 }  // namespace
 }  // namespace fgt
 
@@ -295,6 +326,7 @@ const char* fgt_strerror(int status) {
     case FGT_ENONFINITE: return "non-finite coordinate";
     case FGT_EDEVICE: return "HIP runtime error";
     case FGT_EUNSORTED: return "points not in ascending order";
+    case FGT_ENOSPACE: return "problem larger than the fixed workspace of fgt_eval_noalloc";
     default: return "unknown status";
   }
 }
@@ -352,6 +384,18 @@ size_t fgt_workspace_size(fgt_plan_t plan, int64_t M, int64_t N) {
 int fgt_eval(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha,
              int64_t N, void* u, void* ws, size_t ws_bytes, hipStream_t stream) {
   return fgt::eval_entry(plan, x, M, y, alpha, N, u, ws, ws_bytes, stream, fgt::g_prof.on);
+}
+
+int fgt_eval_noalloc(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha,
+                     int64_t N, void* u, hipStream_t stream) {
+  if (!plan || M < 0 || N < 0) return FGT_EINVAL;
+  if (M + N >= (int64_t(1) << 32)) return FGT_EINVAL;
+  if (fgt_workspace_size(plan, M, N) > (size_t)FGT_NOALLOC_BYTES) return FGT_ENOSPACE;
+  if (M == 0) return FGT_OK;
+  void* ws = nullptr;
+  const int rc = fgt::scratch_of_stream(stream, &ws);
+  if (rc != FGT_OK) return rc;
+  return fgt::eval_entry(plan, x, M, y, alpha, N, u, ws, (size_t)FGT_NOALLOC_BYTES, stream, false);
 }
 
 int fgt_sort(fgt_plan_t plan, const void* x, int64_t M, const void* y, const void* alpha, int64_t N,

@@ -202,6 +202,29 @@ def test_batch_workspace_size_grows_with_points_and_columns():
     assert lib.fgt_eval_batched_workspace_size(3, _i64p(xo), _i64p(yo), 4, 0) == 0
 
 
+def test_noalloc_host_checks():
+    """fgt_eval_noalloc's host checks: the limit is the header's, sizes are refused
+    before any HIP call (no device needed here)."""
+    text = open(HEADER).read()
+    m = re.search(r"#define FGT_NOALLOC_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.FGT_NOALLOC_BYTES
+    lib = _lib.load()
+    p = fgt.plan(1e-3, 6)
+    assert lib.fgt_eval_noalloc(None, None, 10, None, None, 10, None, None) == _lib.FGT_EINVAL
+    assert lib.fgt_eval_noalloc(p.handle, None, -1, None, None, 5, None, None) == _lib.FGT_EINVAL
+    assert (lib.fgt_eval_noalloc(p.handle, None, 1_000_000, None, None, 1_000_000, None, None)
+            == _lib.FGT_ENOSPACE)
+    assert lib.fgt_eval_noalloc(p.handle, None, 0, None, None, 5, None, None) == _lib.FGT_OK
+    # the header states that 1.5e6 points fit at any digits, FP64 and FP32
+    import torch
+    for dt in (torch.float64, torch.float32):
+        for d in range(1, fgt.max_digits(dt) + 1):
+            q = fgt.plan(1e-3, d, dt)
+            assert q.workspace_size(750_000, 750_000) <= _lib.FGT_NOALLOC_BYTES
+            assert q.workspace_size(1_000_000, 1_000_000) > _lib.FGT_NOALLOC_BYTES or dt == torch.float32
+    assert "fixed workspace" in _lib.strerror(_lib.FGT_ENOSPACE)
+
+
 @pytest.mark.parametrize("digits", [3, 4, 6, 9, 11])
 @pytest.mark.parametrize("delta", [1e-6, 1e-3, 1.0])
 def test_sort_resolution_from_oracle_table(delta, digits, otables):
