@@ -507,7 +507,7 @@ def main():
         "k_reduce": scan_read,
     }
     launches = {"k_onesweep": max(n_run, 1), "k_final": 1, "k_reduce": 1}
-    counter_name = {"k_onesweep": "k_onesweep", "k_final": "k_final_fast", "k_reduce": "k_reduce"}
+    counter_name = {"k_onesweep": "k_onesweep", "k_final": "k_wfinal_fast", "k_reduce": "k_wreduce"}
 
     def roof(kernel):
         ms_launch = groups[kernel] / launches[kernel]

@@ -41,8 +41,10 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   const int digits = esz == 8 ? 8 : 4;
   w.sort_tiles = (P + kSortTile - 1) / kSortTile;
   w.scan_tiles = (P + kScanTile - 1) / kScanTile;
+  w.wave_tiles = (P + kWTile - 1) / kWTile;
   if (w.sort_tiles < 1) w.sort_tiles = 1;
   if (w.scan_tiles < 1) w.scan_tiles = 1;
+  if (w.wave_tiles < 1) w.wave_tiles = 1;
   char* b = (char*)base;
   size_t off = 0;
   auto take = [&](size_t bytes) -> void* {
@@ -61,14 +63,21 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   w.lookback[1] = (uint64_t*)take(sizeof(uint64_t) * (size_t)w.sort_tiles * kSortRadix);
   w.dig_off = (uint32_t*)take(sizeof(uint32_t) * digits * kSortRadix);
   w.pass = (PassInfo*)take(sizeof(PassInfo));
-  // Scan state for up to 2 x n_modes scans (the adjoint runs two strength channels).
-  const size_t nq = 2 * (size_t)n_modes;
-  w.agg = take((size_t)esz * kAggStride * nq * (size_t)w.scan_tiles);
-  w.tile_k = (int32_t*)take(sizeof(int32_t) * (size_t)w.scan_tiles);
-  w.carry = take((size_t)esz * 4 * nq * (size_t)w.scan_tiles);
-  const int64_t chunks = (w.scan_tiles + kWave - 1) / kWave;
-  w.chunk_agg = take((size_t)esz * 6 * nq * (size_t)chunks);
-  w.chunk_carry = take((size_t)esz * 4 * nq * (size_t)chunks);
+  // Scan state: the forward's n_modes scans over wave_tiles tiles, or the
+  // adjoint's 2 x n_modes scans (two strength channels) over scan_tiles tiles.
+  const size_t nm = (size_t)n_modes;
+  const size_t tq_fwd = nm * (size_t)w.wave_tiles;
+  const size_t tq_adj = 2 * nm * (size_t)w.scan_tiles;
+  const size_t tq = tq_fwd > tq_adj ? tq_fwd : tq_adj;
+  const size_t cq_fwd = nm * (size_t)((w.wave_tiles + kWave - 1) / kWave);
+  const size_t cq_adj = 2 * nm * (size_t)((w.scan_tiles + kWave - 1) / kWave);
+  const size_t cq = cq_fwd > cq_adj ? cq_fwd : cq_adj;
+  w.agg = take((size_t)esz * kAggStride * tq);
+  w.tile_k = (int32_t*)take(sizeof(int32_t) * (size_t)(w.wave_tiles > w.scan_tiles ? w.wave_tiles
+                                                                                  : w.scan_tiles));
+  w.carry = take((size_t)esz * 4 * tq);
+  w.chunk_agg = take((size_t)esz * 6 * cq);
+  w.chunk_carry = take((size_t)esz * 4 * cq);
   w.tile_part = (double*)take(sizeof(double) * (size_t)w.scan_tiles);
   w.keys[0] = take((size_t)esz * (size_t)P);
   w.keys[1] = take((size_t)esz * (size_t)P);

@@ -93,7 +93,9 @@ constexpr int kHistBlocks = 2048;
 constexpr int kScanThreads = 256;
 constexpr int kScanWaves = kScanThreads / kWave;
 constexpr int kScanChunk = 8;
-constexpr int kScanTile = kScanThreads * kScanChunk;   // 2048 points per tile
+constexpr int kScanTile = kScanThreads * kScanChunk;   // 2048 points per tile (adjoint)
+// Forward scan: a tile is one wave, kScanChunk consecutive points per lane.
+constexpr int kWTile = kWave * kScanChunk;             // 512 points per tile
 constexpr int kCarryThreads = 1024;
 // Per tile and mode the reduce kernel stores A, F, G and the two factors
 // exp(-tau hf), exp(-tau hg) that move the tile carries to its centre.
@@ -291,14 +293,14 @@ struct Workspace {
   uint64_t* lookback[2]; // [sort_tiles][256]; [0] zeroed per call, each pass clears the other
   uint32_t* dig_off;     // [digits][256]
   PassInfo* pass;
-  void* agg;             // [scan_tiles][scans][kAggStride] scalars (complex A, F, G, eF, eG);
-                         // scans = modes for the transform, 2 x modes for its adjoint
-  int32_t* tile_k;       // [scan_tiles] moments used for the tile, -1 if it is too wide
-  void* carry;           // [scan_tiles][modes][4] scalars: CF, CB (complex)
+  void* agg;             // [tiles][scans][kAggStride] scalars (complex A, F, G, eF, eG): the
+                         // forward's wave_tiles x modes, or the adjoint's scan_tiles x 2 modes
+  int32_t* tile_k;       // [tiles] moments used for the tile, -1 if it is too wide
+  void* carry;           // [tiles][scans][4] scalars: CF, CB (complex)
   void* chunk_agg;       // [chunks][modes][6]: composed (A, F, G) of 64 consecutive tiles
   void* chunk_carry;     // [chunks][modes][4]: CF, CB entering each chunk
   size_t zero_bytes;     // bytes from `status` that the first kernel clears
-  int64_t sort_tiles, scan_tiles;
+  int64_t sort_tiles, scan_tiles, wave_tiles;   // radix tiles, adjoint scan tiles, forward scan tiles
   size_t total;
 };
 

@@ -9,12 +9,6 @@
 // and the backward recurrence (4.6), exclusive of the point itself, is
 //     h-_{p-1} = e_p (h-_p + b_p).
 // One factor e_p serves both.  At a target u_p = sum_k Re(omega_k (h+_p + h-_p)), (4.1).
-// The same sweeps give the x-derivative of the transform: h+ holds the sources
-// to the left (sign +1), h- those to the right (sign -1), so
-//     u'_p = sum_k Re(-tau_k omega_k (h+_p - h-_p)).
-// The gradients of L = sum_i g_i u_i are such scans with the roles of sources
-// and targets kept (dL/dx) or swapped (dL/dalpha, dL/dy: strengths g at the
-// targets, outputs at the sources).
 //
 // A segment [s, e) of the sequence acts on the two recurrences as
 //     h+_{e-1} = A h+_{s-1} + F,          h-_{s-1} = A h-_{e-1} + G,
@@ -22,174 +16,291 @@
 //     F = sum_{q in seg} b_q exp(-tau (z_{e-1} - z_q)),   G = sum_{q in seg} b_q exp(-tau (z_q - z_{s-1})),
 // and segments compose associatively:  (A1,F1,G1).(A2,F2,G2) = (A1 A2, A2 F1 + F2, G1 + A1 G2).
 //
-// Three kernels, reduce-then-scan over tiles of kScanTile points:
-//   k_reduce   one wave per tile: the tile's (A, F, G) for every mode.  When the
-//              tile is short on the decay scale (|tau| times its half-width small)
-//              the sums come from mode-independent power moments of the strengths
-//              about the tile centre c:  sum_q b_q exp(+-tau (z_q - c)) =
-//              sum_m (+-tau)^m mu_m / m!,  mu_m = sum_q b_q (z_q - c)^m;
-//              otherwise from the recurrences themselves.
-//   k_carry_* per mode: exclusive prefix of F and suffix of G over tiles.
-//   k_final    per tile: chunk -> wave -> tile scans of both recurrences with
-//              the carries, sweeps, mode reduction, scatter to the outputs.
+// Reduce-then-scan over tiles of kWTile points.  A tile is one wave: lane l
+// holds the kScanChunk consecutive points [t0 + l C, t0 + (l + 1) C), read
+// straight into registers, so the kernels need no LDS and no barrier (a block
+// of 256 threads runs 4 independent tiles):
+//   k_wreduce     the tile's (A, F, G) for every mode.  When the tile is short on
+//                 the decay scale (|tau| times its half-width small) the sums come
+//                 from mode-independent power moments of the strengths about the
+//                 tile centre c:  sum_q b_q exp(+-tau (z_q - c)) =
+//                 sum_m (+-tau)^m mu_m / m!,  mu_m = sum_q b_q (z_q - c)^m;
+//                 otherwise from the recurrences themselves.
+//   carries       per mode: exclusive prefix of F and suffix of G over tiles.
+//   k_wfinal_fast tiles short on the decay scale: the value entering each lane's
+//                 chunk from the moments of the tile's other chunks, both sweeps,
+//                 the sum over modes, scatter to the outputs.
+//   k_wfinal      the other tiles: lane maps, wave scans of both recurrences.
+// The number of moments is a compile-time constant in every loop (the tile's
+// count rounded up to one of a few values), so no loop runs masked slots.
 #include "fgt_device.h"
 
 namespace fgt {
 namespace {
 
-// ---------------------------------------------------------------------------
-// k_reduce: (A, F, G) of every tile and mode.  One wave per tile.
-// ---------------------------------------------------------------------------
-template <class T, int NM>
-__global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void* keys1,
-                                                  const PassInfo* __restrict__ pass,
-                                                  const T* __restrict__ bs, int64_t P, Modes md,
-                                                  T* __restrict__ agg,
-                                                  int32_t* __restrict__ tile_k) {
-  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
-  const int lane = threadIdx.x;
-  const int64_t tile = blockIdx.x;
-  const int64_t t0 = tile * kScanTile;
-  const int n = (int)((P - t0) < kScanTile ? (P - t0) : kScanTile);
-  const T zfirst = keys(t0);
-  const T zprev = t0 > 0 ? keys(t0 - 1) : zfirst;
-  const T zlast = keys(t0 + n - 1);
-  // Centre c and the exact distances to the tile's outer reference points.
-  const T c = zprev + (zlast - zprev) * T(0.5);
-  const T hf = zlast - c;
-  const T hg = c - zprev;
-  const T span = zlast - zprev;
-  const T r = T(md.tau_abs_max) * (hf > hg ? hf : hg);
+// Moment counts the kernels are compiled for; a tile takes the smallest that
+// is not below its own count.
+constexpr int kKSteps[] = {2, 4, 6, 8, 12, 16, 20};
+static_assert(kKSteps[4] == kFastMoments, "the fast final kernel serves counts up to kFastMoments");
 
-  // Number of moments: the series tail r^{K+1}/(K+1)! e^r must be below the unit roundoff.
+__device__ __forceinline__ int k_class(int K) {
+  int c = 0;
+#pragma unroll
+  for (int i = 6; i >= 0; --i)
+    if (K <= kKSteps[i]) c = i;
+  return c;
+}
+
+// Moments needed for a tile whose points lie within r / max|tau| of its
+// centre: the series tail r^{K+1}/(K+1)! e^r must be below the unit roundoff;
+// -1 when kMomentMax terms are not enough.
+template <class T>
+__device__ __forceinline__ int moment_count(T r) {
   int K = 0;
-  {
-    const T er = exp_t(r);
-    T t = r;
-    while (t * er > T(Prec<T>::kUnit) && K < kMomentMax) {
-      ++K;
-      t *= r / T(K + 1);
-    }
-    if (t * er > T(Prec<T>::kUnit)) K = -1;   // too wide: use the recurrences
+  const T er = exp_t(r);
+  T t = r;
+  while (t * er > T(Prec<T>::kUnit) && K < kMomentMax) {
+    ++K;
+    t *= r / T(K + 1);
   }
-  if (lane == 0) tile_k[tile] = K;
+  return t * er > T(Prec<T>::kUnit) ? -1 : K;
+}
 
+// A lane's chunk of the tile: coordinates, strengths (and merged ids),
+// loaded with 16-byte loads when the arrays allow it.  The loads are cached:
+// the lanes of a wave read 64 bytes apart, so each line serves several of
+// the loads (with the nontemporal hint the kernels ran 15-30% slower).
+// Points past the end read as z = 0, b = 0, id = kNoSlot.
+template <class T>
+__device__ __forceinline__ void load_chunk(const T* __restrict__ z, const T* __restrict__ b,
+                                           int64_t base, int64_t P, bool vec, T* zc, T* bc) {
+  constexpr int C = kScanChunk;
+  if (vec && base + C <= P) {
+    typedef T V __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int L = 16 / sizeof(T);
+    const V* pz = reinterpret_cast<const V*>(z + base);
+    const V* pb = reinterpret_cast<const V*>(b + base);
+#pragma unroll
+    for (int q = 0; q < C / L; ++q) {
+      const V vz = pz[q];
+      const V vb = pb[q];
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        zc[q * L + i] = vz[i];
+        bc[q * L + i] = vb[i];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int64_t p = base + j;
+      zc[j] = p < P ? z[p] : T(0);
+      bc[j] = p < P ? b[p] : T(0);
+    }
+  }
+}
+
+__device__ __forceinline__ void load_ids(const uint32_t* __restrict__ ids, int64_t base, int64_t P,
+                                         bool vec, uint32_t* ic) {
+  constexpr int C = kScanChunk;
+  if (vec && base + C <= P) {
+    typedef uint32_t V __attribute__((ext_vector_type(4)));
+    const V* pi = reinterpret_cast<const V*>(ids + base);
+#pragma unroll
+    for (int q = 0; q < C / 4; ++q) {
+      const V v = pi[q];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ic[q * 4 + i] = v[i];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < C; ++j) ic[j] = base + j < P ? ids[base + j] : kNoSlot;
+  }
+}
+
+// Geometry of a wave's tile.  zs: the point before the lane's chunk (the
+// tile's previous point for lane 0); ze: the lane's last point (the tile's
+// last point for a lane past the end); dz, sc: gaps and offsets from the tile
+// centre c (0 for points past the end).
+template <class T>
+struct TileGeo {
+  T zprev, zlast, c, hf, hg, span, zs, ze, dzmax;
+  int n;   // points in the tile
+};
+
+template <class T>
+__device__ __forceinline__ TileGeo<T> tile_geometry(const T* __restrict__ z, int64_t t0, int64_t P,
+                                                    int lane, const T* zc, T* dz, T* sc) {
+  constexpr int C = kScanChunk;
+  TileGeo<T> g;
+  g.n = (int)((P - t0) < kWTile ? (P - t0) : kWTile);
+  const T zfirst = z[t0];
+  g.zprev = t0 > 0 ? z[t0 - 1] : zfirst;
+  const int e0 = lane * C;
+  // last valid point of the lane (or the point before its chunk when it has none)
+  T zl_own = zc[0];
+#pragma unroll
+  for (int j = 1; j < C; ++j)
+    if (e0 + j < g.n) zl_own = zc[j];
+  g.zlast = __shfl(zl_own, (g.n - 1) / C, kWave);
+  if (e0 >= g.n) zl_own = g.zlast;   // lanes past the end: empty chunks at the last point
+  const T up = shfl_up(zl_own, 1);
+  g.zs = lane == 0 ? g.zprev : up;
+  g.ze = zl_own;
+  g.c = g.zprev + (g.zlast - g.zprev) * T(0.5);
+  g.hf = g.zlast - g.c;
+  g.hg = g.c - g.zprev;
+  g.span = g.zlast - g.zprev;
+  T zl = g.zs;
+  T dm = T(0);
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const bool valid = e0 + j < g.n;
+    dz[j] = valid ? zc[j] - zl : T(0);
+    sc[j] = valid ? zc[j] - g.c : T(0);
+    zl = valid ? zc[j] : zl;
+    dm = dz[j] > dm ? dz[j] : dm;
+  }
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) {
+    const T other = shfl_xor(dm, o);
+    dm = other > dm ? other : dm;
+  }
+  g.dzmax = dm;
+  return g;
+}
+
+// exp(-tau dz_j) for the chunk's gaps: the Taylor polynomial of the wave's
+// degree (the smallest whose truncation at the wave's largest gap is below the
+// unit roundoff), the library functions for gaps beyond its range.
+template <class T>
+__device__ __forceinline__ void mode_exps(const Modes& md, int k, const T* dz, T dzmax,
+                                          C<T>* ex) {
+  const double rr = md.tau_abs[k] * (double)dzmax;
+  int D = kTaylorMax;
+#pragma unroll
+  for (int d = kTaylorMax; d >= 1; --d)
+    if (rr <= md.taylor_thr[d]) D = d;
+#pragma unroll
+  for (int j = 0; j < kScanChunk; ++j) ex[j] = {T(0), T(0)};
+#pragma unroll
+  for (int m = kTaylorMax; m >= 0; --m) {
+    if (m <= D) {
+      const T c_re = T(md.coef_re[k][m]), c_im = T(md.coef_im[k][m]);
+#pragma unroll
+      for (int j = 0; j < kScanChunk; ++j) {
+        ex[j].re = fma(ex[j].re, dz[j], c_re);
+        ex[j].im = fma(ex[j].im, dz[j], c_im);
+      }
+    }
+  }
+  const T dz_lim = T(md.dz_lim[k]);
+#pragma unroll
+  for (int j = 0; j < kScanChunk; ++j)
+    if (dz[j] > dz_lim) ex[j] = exp_neg_general<T>(T(md.tau_re[k]), T(md.tau_im[k]), dz[j]);
+}
+
+// ---------------------------------------------------------------------------
+// k_wreduce: (A, F, G, e^{-tau hf}, e^{-tau hg}) of every tile and mode.
+// ---------------------------------------------------------------------------
+template <class T, int NM, int KK>
+__device__ __forceinline__ void reduce_moments(const Modes& md, const T* bc, const T* sc,
+                                               const TileGeo<T>& g, int lane,
+                                               T* __restrict__ out) {
+  T mu[KK + 1];
+#pragma unroll
+  for (int m = 0; m <= KK; ++m) mu[m] = T(0);
+#pragma unroll
+  for (int j = 0; j < kScanChunk; ++j) {
+    T pw = bc[j];
+    mu[0] += pw;
+#pragma unroll
+    for (int m = 1; m <= KK; ++m) {
+      pw *= sc[j];
+      mu[m] += pw;
+    }
+  }
+  // Butterfly sums: every lane ends with the same, order-fixed totals.
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int m = 0; m <= KK; ++m) mu[m] += shfl_xor(mu[m], o);
+  }
+  if (lane < NM) {
+    const int k = lane;
+    const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
+    C<T> fs = {mu[KK] * T(kInvFact.v[KK]), T(0)};
+    C<T> gs = fs;
+#pragma unroll
+    for (int m = KK - 1; m >= 0; --m) {
+      const C<T> cm = {mu[m] * T(kInvFact.v[m]), T(0)};
+      fs = cfma(fs, C<T>{tr, ti}, cm);      // sum (tau)^m mu_m / m!
+      gs = cfma(gs, C<T>{-tr, -ti}, cm);    // sum (-tau)^m mu_m / m!
+    }
+    const C<T> ef = exp_neg_general<T>(tr, ti, g.hf);
+    const C<T> eg = exp_neg_general<T>(tr, ti, g.hg);
+    const C<T> a = exp_neg_general<T>(tr, ti, g.span);
+    const C<T> f = cmul(ef, fs);
+    const C<T> gg = cmul(eg, gs);
+    T* o = out + k * kAggStride;
+    o[0] = a.re; o[1] = a.im;
+    o[2] = f.re; o[3] = f.im;
+    o[4] = gg.re; o[5] = gg.im;
+    o[6] = ef.re; o[7] = ef.im;
+    o[8] = eg.re; o[9] = eg.im;
+  }
+}
+
+template <class T, int NM>
+__global__ __launch_bounds__(256) void k_wreduce(const void* keys0, const void* keys1,
+                                                 const PassInfo* __restrict__ pass,
+                                                 const T* __restrict__ bs, int64_t P,
+                                                 int64_t tiles, int vec, Modes md,
+                                                 T* __restrict__ agg,
+                                                 int32_t* __restrict__ tile_k) {
+  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
+  const int lane = threadIdx.x % kWave;
+  const int64_t tile = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+  if (tile >= tiles) return;
+  const int64_t t0 = tile * kWTile;
+  T zc[kScanChunk], bc[kScanChunk], dz[kScanChunk], sc[kScanChunk];
+  load_chunk(keys.z, bs, t0 + lane * kScanChunk, P, vec != 0, zc, bc);
+  const TileGeo<T> g = tile_geometry(keys.z, t0, P, lane, zc, dz, sc);
+  const int K = moment_count(T(md.tau_abs_max) * (g.hf > g.hg ? g.hf : g.hg));
+  if (lane == 0) tile_k[tile] = K;
+  T* out = agg + (size_t)tile * NM * kAggStride;
   if (K >= 0) {
-    T mu[kMomentMax + 1];
-#pragma unroll
-    for (int m = 0; m <= kMomentMax; ++m) mu[m] = T(0);
-    // The lane's points in order, kGrp at a time with all their loads issued
-    // before any is used.  The loads are nontemporal: the final kernel reads
-    // these arrays again, but they are far larger than the caches.
-    constexpr int kGrp = 8;
-#pragma unroll 1
-    for (int g0 = 0; g0 < kScanTile / kWave; g0 += kGrp) {
-      T zg[kGrp], bg[kGrp];
-#pragma unroll
-      for (int i = 0; i < kGrp; ++i) {
-        const int e = lane + (g0 + i) * kWave;
-        const bool in = e < n;
-        zg[i] = in ? __builtin_nontemporal_load(&keys.z[t0 + e]) : c;
-        bg[i] = in ? __builtin_nontemporal_load(&bs[t0 + e]) : T(0);
-      }
-#pragma unroll
-      for (int i = 0; i < kGrp; ++i) {
-        const T s = zg[i] - c;
-        T pw = bg[i];
-        mu[0] += pw;
-#pragma unroll
-        for (int m = 1; m <= kMomentMax; ++m) {
-          if (m <= K) {
-            pw *= s;
-            mu[m] += pw;
-          }
-        }
-      }
-    }
-    // Butterfly sums: every lane ends with the same, order-fixed totals (the
-    // moments' shuffles interleaved).
-#pragma unroll
-    for (int o = kWave / 2; o >= 1; o >>= 1) {
-#pragma unroll
-      for (int m = 0; m <= kMomentMax; ++m)
-        if (m <= K) mu[m] += shfl_xor(mu[m], o);
-    }
-    if (lane < NM) {
-      const int k = lane;
-      const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
-      T top = T(0);
-#pragma unroll
-      for (int m = 0; m <= kMomentMax; ++m)
-        if (m == K) top = mu[m];
-      C<T> fs = {top * T(kInvFact.v[K]), T(0)};
-      C<T> gs = fs;
-#pragma unroll
-      for (int m = kMomentMax - 1; m >= 0; --m) {
-        if (m < K) {
-          const C<T> cm = {mu[m] * T(kInvFact.v[m]), T(0)};
-          fs = cfma(fs, C<T>{tr, ti}, cm);      // sum (tau)^m mu_m / m!
-          gs = cfma(gs, C<T>{-tr, -ti}, cm);    // sum (-tau)^m mu_m / m!
-        }
-      }
-      const C<T> ef = exp_neg_general<T>(tr, ti, hf);
-      const C<T> eg = exp_neg_general<T>(tr, ti, hg);
-      const C<T> a = exp_neg_general<T>(tr, ti, span);
-      const C<T> f = cmul(ef, fs);
-      const C<T> g = cmul(eg, gs);
-      T* o = agg + ((size_t)tile * NM + k) * kAggStride;
-      o[0] = a.re; o[1] = a.im;
-      o[2] = f.re; o[3] = f.im;
-      o[4] = g.re; o[5] = g.im;
-      o[6] = ef.re; o[7] = ef.im;
-      o[8] = eg.re; o[9] = eg.im;
+    switch (k_class(K)) {
+      case 0: reduce_moments<T, NM, kKSteps[0]>(md, bc, sc, g, lane, out); break;
+      case 1: reduce_moments<T, NM, kKSteps[1]>(md, bc, sc, g, lane, out); break;
+      case 2: reduce_moments<T, NM, kKSteps[2]>(md, bc, sc, g, lane, out); break;
+      case 3: reduce_moments<T, NM, kKSteps[3]>(md, bc, sc, g, lane, out); break;
+      case 4: reduce_moments<T, NM, kKSteps[4]>(md, bc, sc, g, lane, out); break;
+      case 5: reduce_moments<T, NM, kKSteps[5]>(md, bc, sc, g, lane, out); break;
+      default: reduce_moments<T, NM, kKSteps[6]>(md, bc, sc, g, lane, out); break;
     }
     return;
   }
-
-  // Wide tile: fold the recurrences over kPer consecutive points per lane,
-  // then compose the lanes' maps in order.
-  constexpr int kPer = kScanTile / kWave;
-  const int e0 = lane * kPer;
-  const int cnt = n - e0 < 0 ? 0 : (n - e0 < kPer ? n - e0 : kPer);
+  // Wide tile: each lane folds its chunk's recurrences, then the lanes' maps
+  // are composed in order.
 #pragma unroll 1
   for (int k = 0; k < NM; ++k) {
-    const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
-    Seg<T> s = seg_identity<T>();
-    // forward map (A, F)
-    T zl = e0 == 0 ? zprev : (cnt > 0 ? keys(t0 + e0 - 1) : zlast);
-    for (int j = 0; j < cnt; ++j) {
-      const T zj = keys(t0 + e0 + j);
-      const C<T> ex = exp_neg_general<T>(tr, ti, zj - zl);
-      s.a = cmul(s.a, ex);
-      s.f = cfma(ex, s.f, C<T>{bs[t0 + e0 + j], T(0)});
-      zl = zj;
+    C<T> ex[kScanChunk];
+    mode_exps(md, k, dz, g.dzmax, ex);
+    Seg<T> s;
+    s.a = ex[0];
+    s.f = {bc[0], T(0)};
+#pragma unroll
+    for (int j = 1; j < kScanChunk; ++j) {
+      s.a = cmul(s.a, ex[j]);
+      s.f = cfma(ex[j], s.f, C<T>{bc[j], T(0)});
     }
-    // backward map G, last point first
-    C<T> g = {T(0), T(0)};
-    for (int j = cnt - 1; j >= 0; --j) {
-      const T zj = keys(t0 + e0 + j);
-      const T zb = (e0 + j == 0) ? zprev : keys(t0 + e0 + j - 1);
-      const C<T> ex = exp_neg_general<T>(tr, ti, zj - zb);
-      g = cmul(ex, cadd(g, C<T>{bs[t0 + e0 + j], T(0)}));
-    }
-    s.g = g;
-    Seg<T> pf = s, sb = s;
-    for (int o = 1; o < kWave; o <<= 1) {
-      Seg<T> l, rr;
-      l.a.re = shfl_up(pf.a.re, o); l.a.im = shfl_up(pf.a.im, o);
-      l.f.re = shfl_up(pf.f.re, o); l.f.im = shfl_up(pf.f.im, o);
-      if (lane >= o) {
-        pf.f = cfma(pf.a, l.f, pf.f);
-        pf.a = cmul(l.a, pf.a);
-      }
-      rr.a.re = shfl_down(sb.a.re, o); rr.a.im = shfl_down(sb.a.im, o);
-      rr.g.re = shfl_down(sb.g.re, o); rr.g.im = shfl_down(sb.g.im, o);
-      if (lane + o < kWave) {
-        sb.g = cfma(sb.a, rr.g, sb.g);
-        sb.a = cmul(sb.a, rr.a);
-      }
-    }
-    T* o = agg + ((size_t)tile * NM + k) * kAggStride;
+    s.g = {T(0), T(0)};
+#pragma unroll
+    for (int j = kScanChunk - 1; j >= 0; --j) s.g = cmul(ex[j], cadd(s.g, C<T>{bc[j], T(0)}));
+    Seg<T> pf, sb;
+    wave_scans(s, lane, pf, sb);
+    T* o = out + k * kAggStride;
     if (lane == kWave - 1) {
       o[0] = pf.a.re; o[1] = pf.a.im;
       o[2] = pf.f.re; o[3] = pf.f.im;
@@ -200,322 +311,59 @@ __global__ __launch_bounds__(kWave) void k_reduce(const void* keys0, const void*
   }
 }
 
-// ---------------------------------------------------------------------------
-// k_final: both sweeps with the carries, mode reduction, scatter.
-// ---------------------------------------------------------------------------
+// Scatter of one chunk's results: point j feeds output id_j - t_lo when that
+// is below t_n (the unsigned compare keeps every write in bounds).
 template <class T>
-struct Staged {
-  T z[kScanTile + kScanTile / kScanChunk];
-  T b[kScanTile + kScanTile / kScanChunk];
-  uint32_t id[kScanTile + kScanTile / kScanChunk];
-};
-
-// Scatter of one chunk's results (see ScanOut).
-template <class T, int OUT>
 __device__ __forceinline__ void scatter_chunk(const ScanOut<T>& out, const uint32_t* ids,
-                                              const T* acc, const T* dacc) {
+                                              const T* acc) {
 #pragma unroll
   for (int j = 0; j < kScanChunk; ++j) {
     const uint32_t o = ids[j] - out.t_lo;
-    if (o < out.t_n) {
-      if (OUT & kOutVal) out.val[o] = acc[j];
-      if (OUT & kOutDer) out.der[o] = out.scale ? dacc[j] * out.scale[o] : dacc[j];
-    }
+    if (o < out.t_n) out.val[o] = acc[j];
   }
 }
 
-__device__ __forceinline__ int lds_pos(int e) { return e + e / kScanChunk; }
-
-template <class T, int NM, int OUT>
-__global__ __launch_bounds__(kScanThreads) void k_final(const void* keys0, const void* keys1,
-                                                        const PassInfo* __restrict__ pass,
-                                                        const T* __restrict__ bs,
-                                                        const uint32_t* __restrict__ ids,
-                                                        int64_t P, Modes md,
-                                                        const T* __restrict__ carry,
-                                                        const int32_t* __restrict__ tile_k,
-                                                        ScanOut<T> out) {
-  {
-    const int K = tile_k[blockIdx.x];
-    if (K >= 0 && K <= kFastMoments) return;   // handled by k_final_fast
-  }
-  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
-  __shared__ Staged<T> st;
-  __shared__ Seg<T> wtot[NM][kScanWaves][2];   // per wave: [0] forward total, [1] backward total
-  const int tid = threadIdx.x;
-  const int wave = tid / kWave;
-  const int lane = tid % kWave;
-  const int64_t tile = blockIdx.x;
-  const int64_t t0 = tile * kScanTile;
-
-  {
-    // All of this thread's loads are issued before any is used; they are the
-    // last reads of the sorted points in this call, so they are nontemporal.
-    constexpr int R = kScanTile / kScanThreads;
-    T zr[R], br[R];
-    uint32_t sr[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int64_t p = t0 + tid + r * kScanThreads;
-      const bool in = p < P;
-      zr[r] = in ? __builtin_nontemporal_load(&keys.z[p]) : T(0);
-      br[r] = in ? __builtin_nontemporal_load(&bs[p]) : T(0);
-      sr[r] = in ? __builtin_nontemporal_load(&ids[p]) : kNoSlot;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int q = lds_pos(tid + r * kScanThreads);
-      st.z[q] = zr[r];
-      st.b[q] = br[r];
-      st.id[q] = sr[r];
-    }
-  }
-  T zprev = T(0);
-  if (tid == 0) zprev = t0 > 0 ? keys(t0 - 1) : T(0);
-  __syncthreads();
-
-  // This thread's chunk: gaps dz_j = z_j - z_{j-1} and strengths b_j.
-  const int e0 = tid * kScanChunk;
-  T dz[kScanChunk], bb[kScanChunk];
-  T dzmax = T(0);
-  {
-    const int64_t valid = P - t0;
-    T zl;
-    if (tid == 0)
-      zl = t0 > 0 ? zprev : st.z[lds_pos(0)];
-    else
-      zl = st.z[lds_pos(e0 - 1)];
-#pragma unroll
-    for (int j = 0; j < kScanChunk; ++j) {
-      const int e = e0 + j;
-      const T zj = st.z[lds_pos(e)];
-      dz[j] = (e < valid) ? zj - zl : T(0);
-      bb[j] = st.b[lds_pos(e)];
-      zl = (e < valid) ? zj : zl;
-      dzmax = dz[j] > dzmax ? dz[j] : dzmax;
-    }
-  }
-  // Largest gap in the wave: sets the Taylor degree of the mode exponentials.
-#pragma unroll
-  for (int o = kWave / 2; o >= 1; o >>= 1) {
-    const T other = shfl_xor(dzmax, o);
-    dzmax = other > dzmax ? other : dzmax;
-  }
-
-  T acc[kScanChunk], dacc[kScanChunk];
+// Both sweeps of a chunk for one mode from the values entering it: h+ at the
+// point before the chunk (h) and h- at its last point (g); Re(omega (h+ + h-))
+// is added to acc.
+template <class T>
+__device__ __forceinline__ void sweeps(const C<T>* ex, const T* bc, C<T> h, C<T> g, T om_re,
+                                       T om_im, T* acc) {
 #pragma unroll
   for (int j = 0; j < kScanChunk; ++j) {
-    acc[j] = T(0);
-    dacc[j] = T(0);
+    h = cfma(ex[j], h, C<T>{bc[j], T(0)});
+    acc[j] = fma(om_re, h.re, fma(-om_im, h.im, acc[j]));
   }
-
-#pragma unroll 1
-  for (int k = 0; k < NM; ++k) {
-    const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
-    const T om_re = T(md.om_re[k]), om_im = T(md.om_im[k]);
-    const T dm_re = T(md.dom_re[k]), dm_im = T(md.dom_im[k]);
-    // Degree D: smallest with (|tau| dzmax)^{D+1}/(D+1)! below the unit roundoff.
-    const double rr = md.tau_abs[k] * (double)dzmax;
-    int D = kTaylorMax;
 #pragma unroll
-    for (int d = kTaylorMax; d >= 1; --d)
-      if (rr <= md.taylor_thr[d]) D = d;
-    const T dz_lim = T(md.dz_lim[k]);
-
-    // e_j = sum_{m<=D} (-tau)^m dz_j^m / m!  (Horner in the real variable dz)
-    C<T> ex[kScanChunk];
-#pragma unroll
-    for (int j = 0; j < kScanChunk; ++j) ex[j] = {T(0), T(0)};
-#pragma unroll
-    for (int m = kTaylorMax; m >= 0; --m) {
-      if (m <= D) {
-        const T c_re = T(md.coef_re[k][m]), c_im = T(md.coef_im[k][m]);
-#pragma unroll
-        for (int j = 0; j < kScanChunk; ++j) {
-          ex[j].re = fma(ex[j].re, dz[j], c_re);
-          ex[j].im = fma(ex[j].im, dz[j], c_im);
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < kScanChunk; ++j)
-      if (dz[j] > dz_lim) ex[j] = exp_neg_general<T>(tr, ti, dz[j]);
-
-    // Chunk map.
-    Seg<T> s;
-    s.a = ex[0];
-    s.f = {bb[0], T(0)};
-#pragma unroll
-    for (int j = 1; j < kScanChunk; ++j) {
-      s.a = cmul(s.a, ex[j]);
-      s.f = cfma(ex[j], s.f, C<T>{bb[j], T(0)});
-    }
-    s.g = {T(0), T(0)};
-#pragma unroll
-    for (int j = kScanChunk - 1; j >= 0; --j) s.g = cmul(ex[j], cadd(s.g, C<T>{bb[j], T(0)}));
-
-    // Inclusive forward scan over lanes (prefix) and backward scan (suffix).
-    Seg<T> pf = s, sb = s;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      Seg<T> l;
-      l.a.re = shfl_up(pf.a.re, o); l.a.im = shfl_up(pf.a.im, o);
-      l.f.re = shfl_up(pf.f.re, o); l.f.im = shfl_up(pf.f.im, o);
-      if (lane >= o) {
-        pf.f = cfma(pf.a, l.f, pf.f);
-        pf.a = cmul(l.a, pf.a);
-      }
-      Seg<T> r;
-      r.a.re = shfl_down(sb.a.re, o); r.a.im = shfl_down(sb.a.im, o);
-      r.g.re = shfl_down(sb.g.re, o); r.g.im = shfl_down(sb.g.im, o);
-      if (lane + o < kWave) {
-        sb.g = cfma(sb.a, r.g, sb.g);
-        sb.a = cmul(sb.a, r.a);
-      }
-    }
-    if (lane == kWave - 1) wtot[k][wave][0] = pf;
-    if (lane == 0) wtot[k][wave][1] = sb;
-    __syncthreads();
-
-    const T* cr = carry + ((size_t)tile * NM + k) * 4;
-    C<T> cf = {cr[0], cr[1]};
-    C<T> cb = {cr[2], cr[3]};
-    for (int w = 0; w < wave; ++w) cf = cfma(wtot[k][w][0].a, cf, wtot[k][w][0].f);
-    for (int w = kScanWaves - 1; w > wave; --w) cb = cfma(wtot[k][w][1].a, cb, wtot[k][w][1].g);
-    // exclusive lane prefix / suffix
-    Seg<T> xl, xr;
-    xl.a.re = shfl_up(pf.a.re, 1); xl.a.im = shfl_up(pf.a.im, 1);
-    xl.f.re = shfl_up(pf.f.re, 1); xl.f.im = shfl_up(pf.f.im, 1);
-    xr.a.re = shfl_down(sb.a.re, 1); xr.a.im = shfl_down(sb.a.im, 1);
-    xr.g.re = shfl_down(sb.g.re, 1); xr.g.im = shfl_down(sb.g.im, 1);
-    if (lane > 0) cf = cfma(xl.a, cf, xl.f);
-    if (lane < kWave - 1) cb = cfma(xr.a, cb, xr.g);
-
-    // Forward sweep: h+ at every point of the chunk.
-    C<T> h = cf;
-#pragma unroll
-    for (int j = 0; j < kScanChunk; ++j) {
-      h = cfma(ex[j], h, C<T>{bb[j], T(0)});
-      if (OUT & kOutVal) acc[j] = fma(om_re, h.re, fma(-om_im, h.im, acc[j]));
-      if (OUT & kOutDer) dacc[j] = fma(dm_re, h.re, fma(-dm_im, h.im, dacc[j]));
-    }
-    // Backward sweep: h- (exclusive) at every point.
-    C<T> g = cb;
-#pragma unroll
-    for (int j = kScanChunk - 1; j >= 0; --j) {
-      if (OUT & kOutVal) acc[j] = fma(om_re, g.re, fma(-om_im, g.im, acc[j]));
-      if (OUT & kOutDer) dacc[j] = fma(-dm_re, g.re, fma(dm_im, g.im, dacc[j]));
-      g = cmul(ex[j], cadd(g, C<T>{bb[j], T(0)}));
-    }
+  for (int j = kScanChunk - 1; j >= 0; --j) {
+    acc[j] = fma(om_re, g.re, fma(-om_im, g.im, acc[j]));
+    g = cmul(ex[j], cadd(g, C<T>{bc[j], T(0)}));
   }
-
-  uint32_t myid[kScanChunk];
-#pragma unroll
-  for (int j = 0; j < kScanChunk; ++j) myid[j] = st.id[lds_pos(e0 + j)];
-  scatter_chunk<T, OUT>(out, myid, acc, dacc);
 }
 
 // ---------------------------------------------------------------------------
-// k_final_fast: tiles short on the decay scale (moment count K known from
-// k_reduce).  The carry into each thread's chunk comes from the other chunks'
-// power moments about the tile centre c:
+// k_wfinal_fast: tiles with at most kFastMoments moments.  The value entering
+// each lane's chunk comes from the moments of the tile's other chunks about
+// the tile centre c:
 //   h+ before the chunk  = E_f (CF eG + sum_m tau^m P_m / m!),    E_f = exp(-tau (z_s - c)),
 //   h- at its last point = E_b (CB eF + sum_m (-tau)^m S_m / m!), E_b = exp(-tau (c - z_e)),
-// with P_m / S_m the moments of the tile's points before / after the chunk,
-// CF, CB the tile carries, eF = exp(-tau hf), eG = exp(-tau hg) (from k_reduce).
-// The moments are mode-independent, so only two short Taylor series and two
-// Horner sums per chunk and mode remain besides the sweeps.
+// with P_m / S_m the moments of the tile's points before / after the chunk
+// (exclusive prefix and suffix over the lanes), CF, CB the tile carries and
+// eF = exp(-tau hf), eG = exp(-tau hg) from k_wreduce.
 // ---------------------------------------------------------------------------
-template <class T>
-union FastLds {
-  Staged<T> st;
-  struct {
-    T pre[kFastMoments + 1][kScanThreads];   // moments of the tile's points before each chunk
-    T suf[kFastMoments + 1][kScanThreads];   // ... and after it
-  } mom;
-};
-
-template <class T, int NM, int OUT>
-__global__ __launch_bounds__(kScanThreads) void k_final_fast(
-    const void* keys0, const void* keys1, const PassInfo* __restrict__ pass,
-    const T* __restrict__ bs, const uint32_t* __restrict__ ids, int64_t P, Modes md,
-    const T* __restrict__ agg, const T* __restrict__ carry, const int32_t* __restrict__ tile_k,
-    ScanOut<T> out) {
-  const int64_t tile = blockIdx.x;
-  const int K = tile_k[tile];
-  if (K < 0 || K > kFastMoments) return;
-  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
-  __shared__ FastLds<T> lds;
-  __shared__ T mtot[kFastMoments + 1][kScanWaves];
-  const int tid = threadIdx.x;
-  const int wave = tid / kWave;
-  const int lane = tid % kWave;
-  const int64_t t0 = tile * kScanTile;
-  const int n = (int)((P - t0) < kScanTile ? (P - t0) : kScanTile);
-
-  {
-    // All of this thread's loads are issued before any is used; they are the
-    // last reads of the sorted points in this call, so they are nontemporal.
-    constexpr int R = kScanTile / kScanThreads;
-    T zr[R], br[R];
-    uint32_t sr[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int64_t p = t0 + tid + r * kScanThreads;
-      const bool in = p < P;
-      zr[r] = in ? __builtin_nontemporal_load(&keys.z[p]) : T(0);
-      br[r] = in ? __builtin_nontemporal_load(&bs[p]) : T(0);
-      sr[r] = in ? __builtin_nontemporal_load(&ids[p]) : kNoSlot;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int q = lds_pos(tid + r * kScanThreads);
-      lds.st.z[q] = zr[r];
-      lds.st.b[q] = br[r];
-      lds.st.id[q] = sr[r];
-    }
-  }
-  const T zfirst = keys(t0);
-  const T zprev = t0 > 0 ? keys(t0 - 1) : zfirst;
-  const T zlast = keys(t0 + n - 1);
-  const T c = zprev + (zlast - zprev) * T(0.5);
-  __syncthreads();
-
-  // Chunk: gaps, strengths, offsets from the centre, ids, the point before
-  // it (zs) and its last point (ze).
-  const int e0 = tid * kScanChunk;
-  T dz[kScanChunk], bb[kScanChunk], sc[kScanChunk];
-  uint32_t myid[kScanChunk];
-  T dzmax = T(0);
-  T zl = tid == 0 ? zprev : (e0 - 1 < n ? lds.st.z[lds_pos(e0 - 1)] : zlast);
-  const T zs = zl;
-#pragma unroll
-  for (int j = 0; j < kScanChunk; ++j) {
-    const int e = e0 + j;
-    const bool valid = e < n;
-    const T zj = lds.st.z[lds_pos(e)];
-    dz[j] = valid ? zj - zl : T(0);
-    bb[j] = lds.st.b[lds_pos(e)];
-    sc[j] = valid ? zj - c : T(0);
-    myid[j] = lds.st.id[lds_pos(e)];
-    zl = valid ? zj : zl;
-    dzmax = dz[j] > dzmax ? dz[j] : dzmax;
-  }
-  const T ze = zl;
-#pragma unroll
-  for (int o = kWave / 2; o >= 1; o >>= 1) {
-    const T other = shfl_xor(dzmax, o);
-    dzmax = other > dzmax ? other : dzmax;
-  }
-  __syncthreads();   // the staging area becomes the moment tables
-
-  // Chunk moments nu_m = sum_j b_j (z_j - c)^m, their in-wave inclusive sums
-  // (into pre) and the chunk's own values (into suf) for now.
+template <class T, int NM, int KK>
+__device__ __forceinline__ void final_fast_body(const Modes& md, const T* dz, const T* bc,
+                                                const T* sc, const TileGeo<T>& g, int lane,
+                                                const T* __restrict__ ag,
+                                                const T* __restrict__ cr, T* acc) {
+  // Prefix (before the chunk) and suffix (after it) moments, divided by m!.
+  T pre[KK + 1], suf[KK + 1];
   {
     T pw[kScanChunk];
 #pragma unroll
-    for (int j = 0; j < kScanChunk; ++j) pw[j] = bb[j];
-    for (int m = 0; m <= K; ++m) {
+    for (int j = 0; j < kScanChunk; ++j) pw[j] = bc[j];
+#pragma unroll
+    for (int m = 0; m <= KK; ++m) {
       T nu = T(0);
 #pragma unroll
       for (int j = 0; j < kScanChunk; ++j) {
@@ -528,101 +376,141 @@ __global__ __launch_bounds__(kScanThreads) void k_final_fast(
         const T v = shfl_up(inc, o);
         if (lane >= o) inc += v;
       }
-      if (lane == kWave - 1) mtot[m][wave] = inc;
-      lds.mom.pre[m][tid] = inc;
-      lds.mom.suf[m][tid] = nu;
+      const T tot = __shfl(inc, kWave - 1, kWave);
+      const T exc = shfl_up(inc, 1);
+      const T f = T(kInvFact.v[m]);
+      pre[m] = (lane > 0 ? exc : T(0)) * f;
+      suf[m] = (tot - inc) * f;
     }
   }
-  __syncthreads();
-  for (int m = 0; m <= K; ++m) {
-    T off = T(0), tot = T(0);
-#pragma unroll
-    for (int w = 0; w < kScanWaves; ++w) {
-      const T v = mtot[m][w];
-      if (w < wave) off += v;
-      tot += v;
-    }
-    const T inc = lds.mom.pre[m][tid];
-    const T nu = lds.mom.suf[m][tid];
-    lds.mom.pre[m][tid] = off + (inc - nu);   // before the chunk
-    lds.mom.suf[m][tid] = (tot - off) - inc;  // after the chunk
-  }
-
-  T acc[kScanChunk], dacc[kScanChunk];
-#pragma unroll
-  for (int j = 0; j < kScanChunk; ++j) {
-    acc[j] = T(0);
-    dacc[j] = T(0);
-  }
-  const T xf = zs - c;
-  const T xb = c - ze;
-
+  const T xf = g.zs - g.c;
+  const T xb = g.c - g.ze;
 #pragma unroll 1
   for (int k = 0; k < NM; ++k) {
     const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
-    const T om_re = T(md.om_re[k]), om_im = T(md.om_im[k]);
-    const T dm_re = T(md.dom_re[k]), dm_im = T(md.dom_im[k]);
-
-    // Carries into the chunk.  exp(-tau xf), exp(-tau xb) with |tau x| <= r:
-    // degree K suffices; sum_m tau^m P_m / m! and sum_m (-tau)^m S_m / m! by Horner.
-    C<T> ef = {T(0), T(0)}, eb = {T(0), T(0)}, fs = {T(0), T(0)}, gs = {T(0), T(0)};
-    for (int m = K; m >= 0; --m) {
+    C<T> ef = {T(0), T(0)}, eb = {T(0), T(0)};
+    C<T> fs = {pre[KK], T(0)}, gs = {suf[KK], T(0)};
+#pragma unroll
+    for (int m = KK; m >= 0; --m) {
       const T c_re = T(md.coef_re[k][m]), c_im = T(md.coef_im[k][m]);
       ef.re = fma(ef.re, xf, c_re);
       ef.im = fma(ef.im, xf, c_im);
       eb.re = fma(eb.re, xb, c_re);
       eb.im = fma(eb.im, xb, c_im);
-      const T f = T(kInvFact.v[m]);
-      fs = cfma(fs, C<T>{tr, ti}, C<T>{lds.mom.pre[m][tid] * f, T(0)});
-      gs = cfma(gs, C<T>{-tr, -ti}, C<T>{lds.mom.suf[m][tid] * f, T(0)});
-    }
-    const T* ag = agg + ((size_t)tile * NM + k) * kAggStride;
-    const T* cr = carry + ((size_t)tile * NM + k) * 4;
-    const C<T> tf = cfma(C<T>{cr[0], cr[1]}, C<T>{ag[8], ag[9]}, fs);   // CF eG + fs
-    const C<T> tb = cfma(C<T>{cr[2], cr[3]}, C<T>{ag[6], ag[7]}, gs);   // CB eF + gs
-
-    // Mode exponentials of the chunk's gaps.
-    const double rr = md.tau_abs[k] * (double)dzmax;
-    int D = kTaylorMax;
-#pragma unroll
-    for (int d = kTaylorMax; d >= 1; --d)
-      if (rr <= md.taylor_thr[d]) D = d;
-    const T dz_lim = T(md.dz_lim[k]);
-    C<T> ex[kScanChunk];
-#pragma unroll
-    for (int j = 0; j < kScanChunk; ++j) ex[j] = {T(0), T(0)};
-#pragma unroll
-    for (int m = kTaylorMax; m >= 0; --m) {
-      if (m <= D) {
-        const T c_re = T(md.coef_re[k][m]), c_im = T(md.coef_im[k][m]);
-#pragma unroll
-        for (int j = 0; j < kScanChunk; ++j) {
-          ex[j].re = fma(ex[j].re, dz[j], c_re);
-          ex[j].im = fma(ex[j].im, dz[j], c_im);
-        }
+      if (m < KK) {
+        fs = cfma(fs, C<T>{tr, ti}, C<T>{pre[m], T(0)});
+        gs = cfma(gs, C<T>{-tr, -ti}, C<T>{suf[m], T(0)});
       }
     }
-#pragma unroll
-    for (int j = 0; j < kScanChunk; ++j)
-      if (dz[j] > dz_lim) ex[j] = exp_neg_general<T>(tr, ti, dz[j]);
-
-    C<T> h = cmul(ef, tf);
-#pragma unroll
-    for (int j = 0; j < kScanChunk; ++j) {
-      h = cfma(ex[j], h, C<T>{bb[j], T(0)});
-      if (OUT & kOutVal) acc[j] = fma(om_re, h.re, fma(-om_im, h.im, acc[j]));
-      if (OUT & kOutDer) dacc[j] = fma(dm_re, h.re, fma(-dm_im, h.im, dacc[j]));
-    }
-    C<T> g = cmul(eb, tb);
-#pragma unroll
-    for (int j = kScanChunk - 1; j >= 0; --j) {
-      if (OUT & kOutVal) acc[j] = fma(om_re, g.re, fma(-om_im, g.im, acc[j]));
-      if (OUT & kOutDer) dacc[j] = fma(-dm_re, g.re, fma(dm_im, g.im, dacc[j]));
-      g = cmul(ex[j], cadd(g, C<T>{bb[j], T(0)}));
-    }
+    const T* a = ag + k * kAggStride;
+    const T* c = cr + k * 4;
+    const C<T> tf = cfma(C<T>{c[0], c[1]}, C<T>{a[8], a[9]}, fs);   // CF eG + fs
+    const C<T> tb = cfma(C<T>{c[2], c[3]}, C<T>{a[6], a[7]}, gs);   // CB eF + gs
+    C<T> ex[kScanChunk];
+    mode_exps(md, k, dz, g.dzmax, ex);
+    sweeps(ex, bc, cmul(ef, tf), cmul(eb, tb), T(md.om_re[k]), T(md.om_im[k]), acc);
   }
+}
 
-  scatter_chunk<T, OUT>(out, myid, acc, dacc);
+template <class T, int NM>
+__global__ __launch_bounds__(256) void k_wfinal_fast(const void* keys0, const void* keys1,
+                                                     const PassInfo* __restrict__ pass,
+                                                     const T* __restrict__ bs,
+                                                     const uint32_t* __restrict__ ids, int64_t P,
+                                                     int64_t tiles, int vec, Modes md,
+                                                     const T* __restrict__ agg,
+                                                     const T* __restrict__ carry,
+                                                     const int32_t* __restrict__ tile_k,
+                                                     ScanOut<T> out) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t tile = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+  if (tile >= tiles) return;
+  const int K = tile_k[tile];
+  if (K < 0 || K > kFastMoments) return;   // k_wfinal's tile
+  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
+  const int64_t t0 = tile * kWTile;
+  const int64_t base = t0 + lane * kScanChunk;
+  T zc[kScanChunk], bc[kScanChunk], dz[kScanChunk], sc[kScanChunk], acc[kScanChunk];
+  uint32_t ic[kScanChunk];
+  load_chunk(keys.z, bs, base, P, vec != 0, zc, bc);
+  load_ids(ids, base, P, vec != 0, ic);
+  const TileGeo<T> g = tile_geometry(keys.z, t0, P, lane, zc, dz, sc);
+#pragma unroll
+  for (int j = 0; j < kScanChunk; ++j) acc[j] = T(0);
+  const T* ag = agg + (size_t)tile * NM * kAggStride;
+  const T* cr = carry + (size_t)tile * NM * 4;
+  switch (k_class(K)) {
+    case 0: final_fast_body<T, NM, kKSteps[0]>(md, dz, bc, sc, g, lane, ag, cr, acc); break;
+    case 1: final_fast_body<T, NM, kKSteps[1]>(md, dz, bc, sc, g, lane, ag, cr, acc); break;
+    case 2: final_fast_body<T, NM, kKSteps[2]>(md, dz, bc, sc, g, lane, ag, cr, acc); break;
+    case 3: final_fast_body<T, NM, kKSteps[3]>(md, dz, bc, sc, g, lane, ag, cr, acc); break;
+    default: final_fast_body<T, NM, kKSteps[4]>(md, dz, bc, sc, g, lane, ag, cr, acc); break;
+  }
+  scatter_chunk(out, ic, acc);
+}
+
+// ---------------------------------------------------------------------------
+// k_wfinal: the other tiles.  Per mode: the lanes' chunk maps, their inclusive
+// prefix (forward) and suffix (backward) over the wave, the tile carries, the
+// sweeps.
+// ---------------------------------------------------------------------------
+template <class T, int NM>
+__global__ __launch_bounds__(256) void k_wfinal(const void* keys0, const void* keys1,
+                                                const PassInfo* __restrict__ pass,
+                                                const T* __restrict__ bs,
+                                                const uint32_t* __restrict__ ids, int64_t P,
+                                                int64_t tiles, int vec, Modes md,
+                                                const T* __restrict__ carry,
+                                                const int32_t* __restrict__ tile_k,
+                                                ScanOut<T> out) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t tile = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+  if (tile >= tiles) return;
+  {
+    const int K = tile_k[tile];
+    if (K >= 0 && K <= kFastMoments) return;   // k_wfinal_fast's tile
+  }
+  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
+  const int64_t t0 = tile * kWTile;
+  const int64_t base = t0 + lane * kScanChunk;
+  T zc[kScanChunk], bc[kScanChunk], dz[kScanChunk], sc[kScanChunk], acc[kScanChunk];
+  uint32_t ic[kScanChunk];
+  load_chunk(keys.z, bs, base, P, vec != 0, zc, bc);
+  load_ids(ids, base, P, vec != 0, ic);
+  const TileGeo<T> g = tile_geometry(keys.z, t0, P, lane, zc, dz, sc);
+#pragma unroll
+  for (int j = 0; j < kScanChunk; ++j) acc[j] = T(0);
+#pragma unroll 1
+  for (int k = 0; k < NM; ++k) {
+    C<T> ex[kScanChunk];
+    mode_exps(md, k, dz, g.dzmax, ex);
+    Seg<T> s;
+    s.a = ex[0];
+    s.f = {bc[0], T(0)};
+#pragma unroll
+    for (int j = 1; j < kScanChunk; ++j) {
+      s.a = cmul(s.a, ex[j]);
+      s.f = cfma(ex[j], s.f, C<T>{bc[j], T(0)});
+    }
+    s.g = {T(0), T(0)};
+#pragma unroll
+    for (int j = kScanChunk - 1; j >= 0; --j) s.g = cmul(ex[j], cadd(s.g, C<T>{bc[j], T(0)}));
+    Seg<T> pf, sb;
+    wave_scans(s, lane, pf, sb);
+    const T* cr = carry + ((size_t)tile * NM + k) * 4;
+    C<T> cf = {cr[0], cr[1]};
+    C<T> cb = {cr[2], cr[3]};
+    // exclusive lane prefix / suffix
+    Seg<T> xl, xr;
+    xl.a.re = shfl_up(pf.a.re, 1); xl.a.im = shfl_up(pf.a.im, 1);
+    xl.f.re = shfl_up(pf.f.re, 1); xl.f.im = shfl_up(pf.f.im, 1);
+    xr.a.re = shfl_down(sb.a.re, 1); xr.a.im = shfl_down(sb.a.im, 1);
+    xr.g.re = shfl_down(sb.g.re, 1); xr.g.im = shfl_down(sb.g.im, 1);
+    if (lane > 0) cf = cfma(xl.a, cf, xl.f);
+    if (lane < kWave - 1) cb = cfma(xr.a, cb, xr.g);
+    sweeps(ex, bc, cf, cb, T(md.om_re[k]), T(md.om_im[k]), acc);
+  }
+  scatter_chunk(out, ic, acc);
 }
 
 template <class T>
@@ -633,38 +521,33 @@ __global__ void k_fill_zero(T* __restrict__ u, int64_t n) {
 }
 
 template <class T>
-hipError_t carry_tiles(const Workspace& w, int nq, hipStream_t s) {
-  return launch_carries<T>(AggMaps<T>{(const T*)w.agg, nq}, w.scan_tiles, nq, (T*)w.chunk_agg,
+hipError_t carry_tiles(const Workspace& w, int64_t tiles, int nq, hipStream_t s) {
+  return launch_carries<T>(AggMaps<T>{(const T*)w.agg, nq}, tiles, nq, (T*)w.chunk_agg,
                            (T*)w.chunk_carry, (T*)w.carry, s);
 }
 
-template <class T, int NM, int OUT>
-hipError_t scan_nm(const Workspace& w, const Modes& md, int64_t P, const T* b,
-                   const ScanOut<T>& out, hipStream_t s, Timeline* tl) {
-  const dim3 grid((unsigned)w.scan_tiles);
-  hipLaunchKernelGGL((k_reduce<T, NM>), grid, dim3(kWave), 0, s, w.keys[0], w.keys[1], w.pass, b,
-                     P, md, (T*)w.agg, w.tile_k);
-  tl->mark(s);
-  (void)carry_tiles<T>(w, NM, s);
-  tl->mark(s);
-  hipLaunchKernelGGL((k_final_fast<T, NM, OUT>), grid, dim3(kScanThreads), 0, s, w.keys[0],
-                     w.keys[1], w.pass, b, w.ids, P, md, (const T*)w.agg, (const T*)w.carry,
-                     w.tile_k, out);
-  hipLaunchKernelGGL((k_final<T, NM, OUT>), grid, dim3(kScanThreads), 0, s, w.keys[0], w.keys[1],
-                     w.pass, b, w.ids, P, md, (const T*)w.carry, w.tile_k, out);
-  tl->mark(s);
-  return hipGetLastError();
-}
+// 16-byte loads of a lane's chunk need 16-byte aligned arrays.
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 template <class T, int NM>
-hipError_t scan_out(const Workspace& w, const Modes& md, int64_t P, const T* b,
-                    const ScanOut<T>& out, hipStream_t s, Timeline* tl) {
-  const int kind = (out.val ? kOutVal : 0) | (out.der ? kOutDer : 0);
-  switch (kind) {
-    case kOutVal: return scan_nm<T, NM, kOutVal>(w, md, P, b, out, s, tl);
-    case kOutVal | kOutDer: return scan_nm<T, NM, kOutVal | kOutDer>(w, md, P, b, out, s, tl);
-    default: return hipErrorInvalidValue;   // the adjoint has its own kernels
-  }
+hipError_t scan_nm(const Workspace& w, const Modes& md, int64_t P, const T* b,
+                   const ScanOut<T>& out, hipStream_t s, Timeline* tl) {
+  const int64_t tiles = (P + kWTile - 1) / kWTile;
+  const dim3 grid((unsigned)((tiles + 3) / 4));
+  const int vec = aligned16(w.keys[0]) && aligned16(w.keys[1]) && aligned16(b) &&
+                  aligned16(w.ids);
+  hipLaunchKernelGGL((k_wreduce<T, NM>), grid, dim3(256), 0, s, w.keys[0], w.keys[1], w.pass, b,
+                     P, tiles, vec, md, (T*)w.agg, w.tile_k);
+  tl->mark(s);
+  (void)carry_tiles<T>(w, tiles, NM, s);
+  tl->mark(s);
+  hipLaunchKernelGGL((k_wfinal_fast<T, NM>), grid, dim3(256), 0, s, w.keys[0], w.keys[1], w.pass,
+                     b, w.ids, P, tiles, vec, md, (const T*)w.agg, (const T*)w.carry, w.tile_k,
+                     out);
+  hipLaunchKernelGGL((k_wfinal<T, NM>), grid, dim3(256), 0, s, w.keys[0], w.keys[1], w.pass, b,
+                     w.ids, P, tiles, vec, md, (const T*)w.carry, w.tile_k, out);
+  tl->mark(s);
+  return hipGetLastError();
 }
 
 template <class T>
@@ -684,14 +567,15 @@ __global__ __launch_bounds__(256) void k_gather(const uint32_t* __restrict__ ids
 template <class T>
 hipError_t scan_points(const Workspace& w, const Modes& md, int64_t P, const T* b,
                        const ScanOut<T>& out, hipStream_t s, Timeline* tl) {
+  if (!out.val || out.der) return hipErrorInvalidValue;   // the adjoint has its own kernels
   switch (md.n) {
-    case 1: return scan_out<T, 1>(w, md, P, b, out, s, tl);
-    case 2: return scan_out<T, 2>(w, md, P, b, out, s, tl);
-    case 3: return scan_out<T, 3>(w, md, P, b, out, s, tl);
-    case 4: return scan_out<T, 4>(w, md, P, b, out, s, tl);
-    case 5: return scan_out<T, 5>(w, md, P, b, out, s, tl);
-    case 6: return scan_out<T, 6>(w, md, P, b, out, s, tl);
-    case 7: return scan_out<T, 7>(w, md, P, b, out, s, tl);
+    case 1: return scan_nm<T, 1>(w, md, P, b, out, s, tl);
+    case 2: return scan_nm<T, 2>(w, md, P, b, out, s, tl);
+    case 3: return scan_nm<T, 3>(w, md, P, b, out, s, tl);
+    case 4: return scan_nm<T, 4>(w, md, P, b, out, s, tl);
+    case 5: return scan_nm<T, 5>(w, md, P, b, out, s, tl);
+    case 6: return scan_nm<T, 6>(w, md, P, b, out, s, tl);
+    case 7: return scan_nm<T, 7>(w, md, P, b, out, s, tl);
     default: return hipErrorInvalidValue;
   }
 }

@@ -2,15 +2,21 @@
 
     python -m paper_1909_09825_amd.profiling trace  <kernel_trace.csv> --command "..." --out F.md
     python -m paper_1909_09825_amd.profiling traffic <fetch counter_collection.csv> <write ...csv>
-            --copy-bytes B --steps S --command "..." --out profiles/traffic_counters.json
+            --copy-bytes B --command "..." --out profiles/traffic_counters.json
+    python -m paper_1909_09825_amd.profiling valu <counter_collection.csv> --command "..."
+            --out profiles/valu_counters.json --md profiles/F.md
 
 `trace` writes a per-kernel table (dispatches, mean duration, and for the
 radix-pass kernel the mean over the dispatches that move data, i.e. the ones
-longer than a twentieth of the longest).  `traffic` turns FETCH_SIZE and
-WRITE_SIZE (KiB per dispatch) into HBM bytes per launch, each scaled by what
-the same counter reads for the plain device copy of `copy_bytes` bytes that
-bench.py runs with --copy-bytes, and records a hash of the kernel sources so
-that bench.py reports the figure only while the kernels are unchanged.
+longer than a twentieth of the longest).  rocprofv3 reports a counter in
+several rows per dispatch (one per hardware instance); they are summed per
+dispatch.  `traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch) into
+HBM bytes per launch, each scaled by what the same counter reads for the plain
+device copy of `copy_bytes` bytes that bench.py runs with --copy-bytes; `valu`
+records the SQ instruction counters per launch of each kernel's largest
+dispatches (the full-size workload) and the fraction of the chip's VALU issue
+slots they fill during the counter run.  Both record a hash of the kernel
+sources so that bench.py uses a figure only while the kernels are unchanged.
 """
 from __future__ import annotations
 
@@ -24,14 +30,22 @@ import re
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
+_SCAN = ["paper_1909_09825_amd/csrc/fgt_scan.hip", "paper_1909_09825_amd/csrc/fgt_device.h",
+         "paper_1909_09825_amd/csrc/fgt_internal.h"]
+_SORT = ["paper_1909_09825_amd/csrc/fgt_sort.hip", "paper_1909_09825_amd/csrc/fgt_internal.h"]
+_ADJ = ["paper_1909_09825_amd/csrc/fgt_adjoint.hip", "paper_1909_09825_amd/csrc/fgt_device.h",
+        "paper_1909_09825_amd/csrc/fgt_internal.h"]
+_BATCH = ["paper_1909_09825_amd/csrc/fgt_batch.hip", "paper_1909_09825_amd/csrc/fgt_device.h",
+          "paper_1909_09825_amd/csrc/fgt_internal.h"]
 KERNEL_SOURCES = {
-    "k_onesweep": ["paper_1909_09825_amd/csrc/fgt_sort.hip", "paper_1909_09825_amd/csrc/fgt_internal.h"],
-    "k_final_fast": ["paper_1909_09825_amd/csrc/fgt_scan.hip", "paper_1909_09825_amd/csrc/fgt_device.h",
-                     "paper_1909_09825_amd/csrc/fgt_internal.h"],
-    "k_reduce": ["paper_1909_09825_amd/csrc/fgt_scan.hip", "paper_1909_09825_amd/csrc/fgt_device.h",
-                 "paper_1909_09825_amd/csrc/fgt_internal.h"],
+    "k_onesweep": _SORT, "k_range": _SORT, "k_histogram": _SORT,
+    "k_wreduce": _SCAN, "k_wfinal_fast": _SCAN, "k_gather": _SCAN,
+    "k_adj_reduce": _ADJ, "k_adj_final_fast": _ADJ,
+    "k_bscan": _BATCH, "k_bucket_sort": _BATCH, "k_seg_scatter": _BATCH,
 }
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
+# VALU issue slots per second: 256 CUs x 4 SIMDs at 2.4 GHz, 4 cycles per wave64 instruction.
+VALU_SLOTS_PER_S = 256 * 4 * 2.4e9 / 4
 
 
 def source_hash(paths) -> str:
@@ -73,37 +87,113 @@ def trace_summary(path, command: str) -> str:
     return "\n".join(lines) + "\n"
 
 
+def main_grid(base: str, grids):
+    """The dispatches that stand for a kernel: its largest grid (the full-size
+    single transform), or for the batched kernels the grid launched most often
+    (the autotuner times other configurations a few times each)."""
+    if base.startswith(("k_bscan", "k_bucket", "k_seg")):
+        cnt = collections.Counter(grids)
+        return max(cnt, key=lambda g: (cnt[g], g))
+    return max(grids)
+
+
 def load_counter(path, counter):
-    vals = collections.defaultdict(list)
+    """{kernel: [(value summed over the dispatch's rows, grid size, duration us)]}."""
+    per = collections.defaultdict(float)
+    meta = {}
     with open(path) as f:
         for r in csv.DictReader(f):
-            if r["Counter_Name"] == counter:
-                vals[short_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+            if r["Counter_Name"] != counter:
+                continue
+            key = (short_name(r["Kernel_Name"]), r["Dispatch_Id"])
+            per[key] += float(r["Counter_Value"])
+            meta[key] = (int(r["Grid_Size"]),
+                         (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    vals = collections.defaultdict(list)
+    for key, v in per.items():
+        vals[key[0]].append((v, *meta[key]))
     return vals
 
 
 def traffic(fetch_csv, write_csv, copy_bytes: int, command: str):
     fetch = load_counter(fetch_csv, "FETCH_SIZE")
     write = load_counter(write_csv, "WRITE_SIZE")
-    f_scale = copy_bytes / (1024.0 * sum(fetch[COPY_KERNEL]))
-    w_scale = copy_bytes / (1024.0 * sum(write[COPY_KERNEL]))
-    out = {"_about": ("HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per "
-                      "dispatch), scaled by the same counters on a plain copy of copy_bytes bytes; "
-                      "for the radix-pass kernel the mean is over the data-moving dispatches"),
+    f_scale = copy_bytes / (1024.0 * max(v for v, _, _ in fetch[COPY_KERNEL]))
+    w_scale = copy_bytes / (1024.0 * max(v for v, _, _ in write[COPY_KERNEL]))
+    out = {"_about": ("HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB, summed "
+                      "over each dispatch's rows), scaled by the same counters on a plain copy of "
+                      "copy_bytes bytes; the mean is over each kernel's dispatches of the largest "
+                      "grid that move data (more than a twentieth of the largest)"),
            "command": command, "copy_bytes": copy_bytes,
            "fetch_scale": f_scale, "write_scale": w_scale}
     for k in fetch:
         b = base_name(k)
         if b not in KERNEL_SOURCES:
             continue
-        fv, wv = fetch[k], write.get(k, [])
-        big_f = [v for v in fv if v > 0.05 * max(fv)]
-        big_w = [v for v in wv if v > 0.05 * max(wv)] if wv else [0.0]
+        grid = main_grid(b, [g for _, g, _ in fetch[k]])
+        fv = [v for v, g, _ in fetch[k] if g == grid]
+        wv = [v for v, g, _ in write.get(k, []) if g == grid] or [0.0]
+        big_f = [v for v in fv if v > 0.05 * max(fv)] or [0.0]
+        big_w = [v for v in wv if v > 0.05 * max(wv)] or [0.0]
         fb = sum(big_f) / len(big_f) * 1024.0 * f_scale
         wb = sum(big_w) / len(big_w) * 1024.0 * w_scale
-        out[b] = {"kernel": k, "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
-                  "sources": KERNEL_SOURCES[b], "source_sha": source_hash(KERNEL_SOURCES[b])}
+        name = b if b not in out else k
+        out[name] = {"kernel": k, "grid": grid, "fetch_bytes": fb, "write_bytes": wb,
+                     "bytes_per_launch": fb + wb, "sources": KERNEL_SOURCES[b],
+                     "source_sha": source_hash(KERNEL_SOURCES[b])}
     return out
+
+
+SQ = ["SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS",
+      "SQ_LDS_BANK_CONFLICT", "SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES"]
+
+
+def valu(csv_path, command: str):
+    """Per kernel (its main grid, see main_grid; data-moving dispatches): SQ counters per launch."""
+    data = {c: load_counter(csv_path, c) for c in SQ}
+    out = {"_about": ("SQ instruction counters per launch (wave instructions, summed over each "
+                      "dispatch's rows) for each kernel's dispatches of its main grid (the largest; "
+                      "for batched kernels the one launched most often) that do work; valu_frac_pmc = SQ_INSTS_VALU x 4 cycles over the chip's VALU issue "
+                      "slots (1024 SIMDs at 2.4 GHz) during the counter run's own dispatch time"),
+           "command": command}
+    for k, rows in data["SQ_INSTS_VALU"].items():
+        b = base_name(k)
+        if b not in KERNEL_SOURCES:
+            continue
+        grid = main_grid(b, [g for _, g, _ in rows])
+        vals = [(v, d) for v, g, d in rows if g == grid]
+        vmax = max(v for v, _ in vals)
+        keep = [(v, d) for v, d in vals if v > 0.05 * vmax] or vals
+        rec = {"kernel": k, "grid": grid, "dispatches": len(keep),
+               "valu_insts_per_launch": sum(v for v, _ in keep) / len(keep),
+               "us_per_launch_pmc": sum(d for _, d in keep) / len(keep)}
+        for c in SQ[1:]:
+            cv = [v for v, g, _ in data[c].get(k, []) if g == grid]
+            cv = sorted(cv)[-len(keep):] if cv else [0.0]
+            rec[c.lower() + "_per_launch"] = sum(cv) / len(cv)
+        rec["valu_frac_pmc"] = rec["valu_insts_per_launch"] / (
+            rec["us_per_launch_pmc"] * 1e-6 * VALU_SLOTS_PER_S)
+        rec["sources"] = KERNEL_SOURCES[b]
+        rec["source_sha"] = source_hash(KERNEL_SOURCES[b])
+        out[k if b in out or b in ("k_bscan",) else b] = rec
+    return out
+
+
+def valu_md(rec: dict) -> str:
+    lines = ["# rocprofv3 SQ counters (VALU, LDS)", "", f"Command: `{rec['command']}`", "",
+             rec["_about"] + ".", "",
+             "| kernel | grid | launches | us/launch (counter run) | VALU insts | VALU issue frac "
+             "| LDS insts | LDS bank conflicts | SALU insts | waves |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    for name, r in rec.items():
+        if name.startswith("_") or name == "command":
+            continue
+        lines.append(f"| `{r['kernel']}` | {r['grid']} | {r['dispatches']} | "
+                     f"{r['us_per_launch_pmc']:.1f} | {r['valu_insts_per_launch']:.4g} | "
+                     f"{r['valu_frac_pmc']:.3f} | {r['sq_insts_lds_per_launch']:.4g} | "
+                     f"{r['sq_lds_bank_conflict_per_launch']:.4g} | "
+                     f"{r['sq_insts_salu_per_launch']:.4g} | {r['sq_waves_per_launch']:.0f} |")
+    return "\n".join(lines) + "\n"
 
 
 def main():
@@ -119,14 +209,26 @@ def main():
     c.add_argument("--copy-bytes", type=int, required=True)
     c.add_argument("--command", required=True)
     c.add_argument("--out", required=True)
+    v = sub.add_parser("valu")
+    v.add_argument("csv")
+    v.add_argument("--command", required=True)
+    v.add_argument("--out", required=True)
+    v.add_argument("--md", required=True)
     a = ap.parse_args()
     if a.cmd == "trace":
         with open(a.out, "w") as f:
             f.write(trace_summary(a.csv, a.command))
-    else:
+    elif a.cmd == "traffic":
         with open(a.out, "w") as f:
             json.dump(traffic(a.fetch_csv, a.write_csv, a.copy_bytes, a.command), f, indent=1)
             f.write("\n")
+    else:
+        rec = valu(a.csv, a.command)
+        with open(a.out, "w") as f:
+            json.dump(rec, f, indent=1)
+            f.write("\n")
+        with open(a.md, "w") as f:
+            f.write(valu_md(rec))
 
 
 if __name__ == "__main__":
