@@ -17,11 +17,12 @@
 //   k_seg_offsets   per transform: exclusive offsets, bucket-major, so the
 //                   split is stable
 //   k_seg_scatter   per chunk: stable ranks inside the chunk, merged indices
-//                   written to their bucket
-//   k_bucket_sort   per bucket: LSD radix sort of its keys in LDS (a bucket
-//                   above kBucketMax points, possible only for very uneven
-//                   data, is sorted by the same block through global memory),
-//                   then the sorted coordinates and the output codes.
+//                   and coordinates written side by side to their bucket
+//   k_bucket_sort   per bucket: LSD radix sort of its keys in LDS, each with
+//                   its position in the bucket (a bucket above kBucketMax
+//                   points, possible only for very uneven data, is sorted by
+//                   the same block through global memory), then the sorted
+//                   coordinates and the output codes read from the bucket.
 // The gaps are scaled only in the scan, (z_p - z_{p-1}) / sqrt(delta_b), so
 // that their rounding error is relative to the gap, as in the single path.
 // Key digits below the allowed sort resolution are not sorted (the same
@@ -236,7 +237,8 @@ __global__ __launch_bounds__(256) void k_seg_scatter(const SegInfo* __restrict__
                                                      const double* __restrict__ lo,
                                                      const double* __restrict__ hi,
                                                      const uint32_t* __restrict__ offs,
-                                                     uint32_t* __restrict__ ids_tmp) {
+                                                     uint32_t* __restrict__ ids_tmp,
+                                                     double* __restrict__ z_tmp) {
   extern __shared__ uint32_t wcnt[];   // [4][nb]
   constexpr int kRounds = kBChunk / 4 / kWave;   // 16
   const ChunkInfo ch = chunks[blockIdx.x];
@@ -292,7 +294,10 @@ __global__ __launch_bounds__(256) void k_seg_scatter(const SegInfo* __restrict__
     const int64_t p = ch.start + (int64_t)wave * (kBChunk / 4) + r * kWave + lane;
     const uint64_t pos = (uint64_t)offs[sg.cnt0 + (int64_t)bk[r] * sg.n_chunks + c] +
                          wcnt[wave * nb + bk[r]] + rank[r];
-    if (pos < (uint64_t)P) ids_tmp[sg.base + (int64_t)pos] = (uint32_t)p;
+    if (pos < (uint64_t)P) {
+      ids_tmp[sg.base + (int64_t)pos] = (uint32_t)p;
+      z_tmp[sg.base + (int64_t)pos] = z[r];
+    }
   }
 }
 
@@ -306,16 +311,21 @@ struct RankLds {
 
 // Stable ranking of up to kBucketMax keys held kBSortItems per thread, items
 // ordered (wave, item, lane), by the 8-bit digit at `shift`.  On return
-// pos[i] is the item's position in digit order, and lds.thist / lds.tstart
-// hold the digit counts and exclusive starts.
+// pos[i] is the item's position in digit order (for valid items), and
+// lds.thist / lds.tstart hold the digit counts and exclusive starts.  A wave
+// with no valid item passes wave_active = false and only joins the barriers.
 __device__ __forceinline__ void block_rank(const uint64_t* key, const bool* valid, int shift,
-                                           uint32_t* pos, RankLds& lds) {
+                                           bool wave_active, uint32_t* pos, RankLds& lds) {
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   constexpr int W = kBSortThreads / kWave;
   for (int i = tid; i < W * kRadix; i += kBSortThreads) (&lds.wcnt[0][0])[i] = 0u;
   if (tid < kRadix) lds.thist[tid] = 0u;
   __syncthreads();
   uint32_t rank[kBSortItems];
+#pragma unroll
+  for (int i = 0; i < kBSortItems; ++i) rank[i] = 0u;
+  // A wave whose items all lie past the end ranks nothing (uniform branch).
+  if (wave_active) {
 #pragma unroll
   for (int i = 0; i < kBSortItems; ++i) {
     const uint32_t dig = (uint32_t)(key[i] >> shift) & 0xffu;
@@ -335,6 +345,7 @@ __device__ __forceinline__ void block_rank(const uint64_t* key, const bool* vali
     if (valid[i] && below == 0u) lds.wcnt[wave][dig] = before + cnt;
     __builtin_amdgcn_wave_barrier();
     rank[i] = before + below;
+  }
   }
   __syncthreads();
   if (tid < kRadix) {
@@ -383,7 +394,8 @@ __global__ __launch_bounds__(kBSortThreads) void k_bucket_sort(
     const SegInfo* __restrict__ seg, const BucketInfo* __restrict__ buckets,
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ lo,
     const double* __restrict__ hi, const uint32_t* __restrict__ bstart,
-    const uint32_t* __restrict__ bsize, const uint32_t* __restrict__ ids_tmp, uint64_t* q0,
+    const uint32_t* __restrict__ bsize, const uint32_t* __restrict__ ids_tmp,
+    const double* __restrict__ z_tmp, uint64_t* q0,
     uint64_t* q1, uint32_t* i0, uint32_t* i1, double s_allow, int64_t SN,
     double* __restrict__ zs, uint32_t* __restrict__ ids, uint32_t* __restrict__ status) {
   __shared__ RankLds rl;
@@ -426,27 +438,26 @@ __global__ __launch_bounds__(kBSortThreads) void k_bucket_sort(
   };
 
   if (n <= (uint32_t)kBucketMax) {
+    // The split left the bucket's merged indices and coordinates side by side
+    // (contiguous loads); the passes sort each key with its index inside the
+    // bucket, and the coordinate and code of every sorted point are read back
+    // from the bucket's own arrays.
     uint64_t key[kBSortItems];
-    uint32_t id[kBSortItems];
+    uint32_t id[kBSortItems];   // position inside the bucket
     bool valid[kBSortItems];
-    // Indices, then the coordinates they point at, then the keys: each group
-    // of loads is issued together.
+    double zk[kBSortItems];
 #pragma unroll
     for (int i = 0; i < kBSortItems; ++i) {
       const int it = item_index(i);
       valid[i] = it < (int)n;
-      id[i] = valid[i] ? ids_tmp[off + it] : 0u;
-    }
-    double zk[kBSortItems];
-#pragma unroll
-    for (int i = 0; i < kBSortItems; ++i) {
-      if (valid[i]) id[i] = checked(id[i]);
-      zk[i] = valid[i] ? seg_point(sg, x, y, id[i]) : 0.0;
+      id[i] = (uint32_t)it;
+      zk[i] = valid[i] ? z_tmp[off + it] : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < kBSortItems; ++i)
       key[i] = valid[i] ? quant_key(zk[i], sg.scale, l, qs) : 0ull;
-    const uint64_t first = point_key(sg, x, y, checked(ids_tmp[off]), l, qs);
+    const bool wave_active = wave * (kBSortItems * kWave) < (int)n;
+    const uint64_t first = quant_key(z_tmp[off], sg.scale, l, qs);
     uint64_t diff = 0ull;
 #pragma unroll
     for (int i = 0; i < kBSortItems; ++i) diff |= valid[i] ? (key[i] ^ first) : 0ull;
@@ -455,7 +466,7 @@ __global__ __launch_bounds__(kBSortThreads) void k_bucket_sort(
     for (int d = 0; d < 8; ++d) {
       if (!needs_pass(diff, d)) continue;
       uint32_t pos[kBSortItems];
-      block_rank(key, valid, 8 * d, pos, rl);
+      block_rank(key, valid, 8 * d, wave_active, pos, rl);
 #pragma unroll
       for (int i = 0; i < kBSortItems; ++i)
         if (valid[i]) stage[pos[i]] = key[i];
@@ -478,8 +489,17 @@ __global__ __launch_bounds__(kBSortThreads) void k_bucket_sort(
       __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < kBSortItems; ++i)
-      if (valid[i]) emit_point(sg, off + item_index(i), id[i], x, y, SN, zs, ids);
+    for (int i = 0; i < kBSortItems; ++i) {
+      if (!valid[i]) continue;
+      const uint32_t local = id[i] < n ? id[i] : n - 1u;
+      const uint32_t p = checked(ids_tmp[off + local]);
+      uint32_t code = (int64_t)p < sg.N ? (uint32_t)(sg.y_off + p)
+                                        : (uint32_t)(SN + sg.x_off + ((int64_t)p - sg.N));
+      const int64_t pos = off + item_index(i);
+      if (pos == sg.base) code |= kSegStart;
+      zs[pos] = z_tmp[off + local];
+      ids[pos] = code;
+    }
     return;
   }
 
@@ -533,7 +553,7 @@ __global__ __launch_bounds__(kBSortThreads) void k_bucket_sort(
         id[i] = valid[i] ? ia[off + it] : 0u;
       }
       uint32_t pos[kBSortItems];
-      block_rank(key, valid, 8 * d, pos, rl);
+      block_rank(key, valid, 8 * d, t0 + (uint32_t)item_index(0) - lane < n, pos, rl);
 #pragma unroll
       for (int i = 0; i < kBSortItems; ++i) {
         if (!valid[i]) continue;
@@ -869,6 +889,7 @@ BatchWork batch_layout(void* base, const BatchDims& d) {
   w.bstart = (uint32_t*)take(sizeof(uint32_t) * (size_t)d.n_buckets);
   w.bsize = (uint32_t*)take(sizeof(uint32_t) * (size_t)d.n_buckets);
   w.ids_tmp = (uint32_t*)take(sizeof(uint32_t) * P);
+  w.z_tmp = (double*)take(sizeof(double) * P);
   w.qbuf[0] = (uint64_t*)take(sizeof(uint64_t) * P);
   w.qbuf[1] = (uint64_t*)take(sizeof(uint64_t) * P);
   w.ibuf[0] = (uint32_t*)take(sizeof(uint32_t) * P);
@@ -907,12 +928,13 @@ hipError_t batch_eval_launch(const BatchDims& d, const BatchTables& t, const Mod
   if (d.n_chunks > 0) {
     hipLaunchKernelGGL(k_seg_scatter, dim3((unsigned)d.n_chunks), dim3(256),
                        4 * nb_max * sizeof(uint32_t), s, seg, chunks, x, y, (const double*)w.lo,
-                       (const double*)w.hi, (const uint32_t*)w.offs, w.ids_tmp);
+                       (const double*)w.hi, (const uint32_t*)w.offs, w.ids_tmp, w.z_tmp);
   }
   hipLaunchKernelGGL(k_bucket_sort, dim3((unsigned)t.n_buckets), dim3(kBSortThreads), 0, s, seg,
                      buckets, x, y, (const double*)w.lo, (const double*)w.hi,
                      (const uint32_t*)w.bstart, (const uint32_t*)w.bsize,
-                     (const uint32_t*)w.ids_tmp, w.qbuf[0], w.qbuf[1], w.ibuf[0], w.ibuf[1],
+                     (const uint32_t*)w.ids_tmp, (const double*)w.z_tmp, w.qbuf[0], w.qbuf[1],
+                     w.ibuf[0], w.ibuf[1],
                      s_allow, d.SN, w.zs, w.ids, w.status);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -412,6 +412,7 @@ struct BatchWork {
   uint32_t* bstart;       // [sum nb] bucket start inside its transform
   uint32_t* bsize;        // [sum nb]
   uint32_t* ids_tmp;      // [P] merged indices after the bucket split
+  double* z_tmp;          // [P] their coordinates (unscaled), beside them
   uint64_t* qbuf[2];      // [P] keys of the block-global path
   uint32_t* ibuf[2];      // [P]
   double* zs;             // [P] sorted coordinates
