@@ -292,21 +292,58 @@ def backward(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor, g: torch.Ten
     return o_da, o_dx, o_dy, o_dd
 
 
+class _WorkspaceCache:
+    """Plans and workspaces of GaussTransform, kept across calls (LRU, a few shapes).
+
+    Key: (delta, digits, dtype, M, N, device).  Each entry counts the forwards
+    that wrote its workspace, so a backward can tell whether the workspace
+    still holds its own forward's sort (then it reuses it) or was taken by a
+    later forward of the same shape (then it sorts again).
+    """
+
+    def __init__(self, capacity: int = 4):
+        import collections
+        self.capacity = capacity
+        self.entries = collections.OrderedDict()
+
+    def get(self, delta: float, digits: int, dtype, M: int, N: int, device):
+        key = (float(delta), int(digits), dtype, int(M), int(N), str(device))
+        ent = self.entries.get(key)
+        if ent is None:
+            p = Plan(delta, digits, dtype)
+            ent = {"plan": p, "ws": workspace(p, M, N, device), "generation": 0}
+            self.entries[key] = ent
+            while len(self.entries) > self.capacity:
+                self.entries.popitem(last=False)
+        else:
+            self.entries.move_to_end(key)
+        return ent
+
+    def clear(self):
+        self.entries.clear()
+
+
+_gt_cache = _WorkspaceCache()
+
+
 class GaussTransform(torch.autograd.Function):
     """u = FGT(x, y, alpha; delta) with gradients in x, y, alpha and delta.
 
     The forward keeps its workspace (the sort of the points) for the backward,
-    which runs the adjoint scans on the same sorted order.
+    which runs the adjoint scans on the same sorted order.  Plans and
+    workspaces are cached across calls by shape, so a training loop allocates
+    them once; if another forward of the same shape ran in between, the
+    backward sorts the points again instead of using the workspace.
     """
 
     @staticmethod
     def forward(ctx, x, y, alpha, delta, digits):
         d = float(delta.detach().item()) if isinstance(delta, torch.Tensor) else float(delta)
-        p = Plan(d, int(digits), x.dtype)
-        ws = workspace(p, x.shape[0], y.shape[0], x.device)
-        u = eval(x, y, alpha, p, ws=ws)
+        ent = _gt_cache.get(d, int(digits), x.dtype, x.shape[0], y.shape[0], x.device)
+        u = eval(x, y, alpha, ent["plan"], ws=ent["ws"])
+        ent["generation"] += 1
         ctx.save_for_backward(x, y, alpha)
-        ctx.plan, ctx.ws = p, ws
+        ctx.entry, ctx.generation = ent, ent["generation"]
         ctx.delta_is_tensor = isinstance(delta, torch.Tensor)
         ctx.delta_dtype = delta.dtype if ctx.delta_is_tensor else None
         return u
@@ -317,8 +354,12 @@ class GaussTransform(torch.autograd.Function):
         nx, ny, na, nd = ctx.needs_input_grad[:4]
         if not (nx or ny or na or nd):
             return None, None, None, None, None
-        da, dx, dy, dd = backward(x, y, alpha, gu.to(x.dtype).contiguous(), ctx.plan, ctx.ws,
-                                  sorted=True, dalpha=na, dx=nx, dy=ny, ddelta=nd)
+        ent = ctx.entry
+        own = ent["generation"] == ctx.generation
+        da, dx, dy, dd = backward(x, y, alpha, gu.to(x.dtype).contiguous(), ent["plan"], ent["ws"],
+                                  sorted=own, dalpha=na, dx=nx, dy=ny, ddelta=nd)
+        if not own:
+            ent["generation"] += 1      # this backward sorted again: the workspace is its now
         if dd is not None and ctx.delta_is_tensor:
             dd = dd.to(ctx.delta_dtype)
         return dx, dy, da, dd, None

@@ -94,8 +94,8 @@ __constant__ constexpr InvFact kInvFact{};
 // mode when two strength channels share the sweeps).  CF[t] = forward value
 // entering tile t from the left (h+ at the point before it), CB[t] = backward
 // value entering from the right (h- at its last point).  Three levels so that
-// the whole chip takes part: tiles are grouped in chunks of 64 (one wave per
-// chunk and scan),
+// the whole chip takes part: tiles are grouped in chunks of 64 (one block per
+// chunk, one wave per scan at a time),
 //   k_carry_up    the composed map of each chunk,
 //   k_carry_top   per scan, the values entering each chunk (sequential runs
 //                 per thread, then a block scan),
@@ -161,23 +161,31 @@ struct BatchMaps {
   }
 };
 
+// k_carry_up and k_carry_down take one chunk of 64 tiles per block and loop
+// over the scans, one wave per scan at a time: the maps of a tile lie together
+// (all scans of a tile in one row), so the rows a block reads stay in cache
+// while its waves walk through the scans.
+constexpr int kCarryWaves = 4;
+
 template <class T, class Maps>
-__global__ __launch_bounds__(kWave) void k_carry_up(Maps maps, int64_t tiles, int nq,
-                                                    T* __restrict__ chunk_agg) {
-  const int lane = threadIdx.x;
-  const int q = blockIdx.y;
+__global__ __launch_bounds__(kWave * kCarryWaves) void k_carry_up(Maps maps, int64_t tiles, int nq,
+                                                                  T* __restrict__ chunk_agg) {
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
   const int64_t chunk = blockIdx.x;
   const int64_t t = chunk * kWave + lane;
-  const Seg<T> s = t < tiles ? maps(t, q) : seg_identity<T>();
-  Seg<T> pf, sb;
-  wave_scans(s, lane, pf, sb);
-  T* o = chunk_agg + ((size_t)chunk * nq + q) * 6;
-  if (lane == kWave - 1) {
-    o[0] = pf.a.re; o[1] = pf.a.im;
-    o[2] = pf.f.re; o[3] = pf.f.im;
-  }
-  if (lane == 0) {
-    o[4] = sb.g.re; o[5] = sb.g.im;
+  for (int q = wave; q < nq; q += kCarryWaves) {
+    const Seg<T> s = t < tiles ? maps(t, q) : seg_identity<T>();
+    Seg<T> pf, sb;
+    wave_scans(s, lane, pf, sb);
+    T* o = chunk_agg + ((size_t)chunk * nq + q) * 6;
+    if (lane == kWave - 1) {
+      o[0] = pf.a.re; o[1] = pf.a.im;
+      o[2] = pf.f.re; o[3] = pf.f.im;
+    }
+    if (lane == 0) {
+      o[4] = sb.g.re; o[5] = sb.g.im;
+    }
   }
 }
 
@@ -233,33 +241,34 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry_top(const T* __restrict
 }
 
 template <class T, class Maps>
-__global__ __launch_bounds__(kWave) void k_carry_down(Maps maps, int64_t tiles, int nq,
-                                                      const T* __restrict__ chunk_carry,
-                                                      T* __restrict__ carry) {
-  const int lane = threadIdx.x;
-  const int q = blockIdx.y;
+__global__ __launch_bounds__(kWave * kCarryWaves) void k_carry_down(
+    Maps maps, int64_t tiles, int nq, const T* __restrict__ chunk_carry, T* __restrict__ carry) {
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
   const int64_t chunk = blockIdx.x;
   const int64_t t = chunk * kWave + lane;
-  const Seg<T> s = t < tiles ? maps(t, q) : seg_identity<T>();
-  Seg<T> pf, sb;
-  wave_scans(s, lane, pf, sb);
-  const T* cc = chunk_carry + ((size_t)chunk * nq + q) * 4;
-  C<T> cf = {cc[0], cc[1]};
-  C<T> cb = {cc[2], cc[3]};
-  // exclusive: the tiles before / after this one inside the chunk
-  Seg<T> xl, xr;
-  xl.a.re = shfl_up(pf.a.re, 1); xl.a.im = shfl_up(pf.a.im, 1);
-  xl.f.re = shfl_up(pf.f.re, 1); xl.f.im = shfl_up(pf.f.im, 1);
-  xr.a.re = shfl_down(sb.a.re, 1); xr.a.im = shfl_down(sb.a.im, 1);
-  xr.g.re = shfl_down(sb.g.re, 1); xr.g.im = shfl_down(sb.g.im, 1);
-  if (lane > 0) cf = cfma(xl.a, cf, xl.f);
-  if (lane < kWave - 1) cb = cfma(xr.a, cb, xr.g);
-  if (t < tiles) {
-    T* o = carry + ((size_t)t * nq + q) * 4;
-    o[0] = cf.re;
-    o[1] = cf.im;
-    o[2] = cb.re;
-    o[3] = cb.im;
+  for (int q = wave; q < nq; q += kCarryWaves) {
+    const Seg<T> s = t < tiles ? maps(t, q) : seg_identity<T>();
+    Seg<T> pf, sb;
+    wave_scans(s, lane, pf, sb);
+    const T* cc = chunk_carry + ((size_t)chunk * nq + q) * 4;
+    C<T> cf = {cc[0], cc[1]};
+    C<T> cb = {cc[2], cc[3]};
+    // exclusive: the tiles before / after this one inside the chunk
+    Seg<T> xl, xr;
+    xl.a.re = shfl_up(pf.a.re, 1); xl.a.im = shfl_up(pf.a.im, 1);
+    xl.f.re = shfl_up(pf.f.re, 1); xl.f.im = shfl_up(pf.f.im, 1);
+    xr.a.re = shfl_down(sb.a.re, 1); xr.a.im = shfl_down(sb.a.im, 1);
+    xr.g.re = shfl_down(sb.g.re, 1); xr.g.im = shfl_down(sb.g.im, 1);
+    if (lane > 0) cf = cfma(xl.a, cf, xl.f);
+    if (lane < kWave - 1) cb = cfma(xr.a, cb, xr.g);
+    if (t < tiles) {
+      T* o = carry + ((size_t)t * nq + q) * 4;
+      o[0] = cf.re;
+      o[1] = cf.im;
+      o[2] = cb.re;
+      o[3] = cb.im;
+    }
   }
 }
 
@@ -268,11 +277,11 @@ template <class T, class Maps>
 hipError_t launch_carries(const Maps& maps, int64_t tiles, int nq, T* chunk_agg, T* chunk_carry,
                           T* carry, hipStream_t s) {
   const int64_t chunks = (tiles + kWave - 1) / kWave;
-  hipLaunchKernelGGL((k_carry_up<T, Maps>), dim3((unsigned)chunks, (unsigned)nq), dim3(kWave), 0, s,
+  hipLaunchKernelGGL((k_carry_up<T, Maps>), dim3((unsigned)chunks), dim3(kWave * kCarryWaves), 0, s,
                      maps, tiles, nq, chunk_agg);
   hipLaunchKernelGGL(k_carry_top<T>, dim3((unsigned)nq), dim3(kCarryThreads), 0, s,
                      (const T*)chunk_agg, chunks, nq, chunk_carry);
-  hipLaunchKernelGGL((k_carry_down<T, Maps>), dim3((unsigned)chunks, (unsigned)nq), dim3(kWave), 0,
+  hipLaunchKernelGGL((k_carry_down<T, Maps>), dim3((unsigned)chunks), dim3(kWave * kCarryWaves), 0,
                      s, maps, tiles, nq, (const T*)chunk_carry, carry);
   return hipGetLastError();
 }

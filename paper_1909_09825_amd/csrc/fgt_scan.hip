@@ -53,11 +53,12 @@ __device__ __forceinline__ int k_class(int K) {
 
 // Moments needed for a tile whose points lie within r / max|tau| of its
 // centre: the series tail r^{K+1}/(K+1)! e^r must be below the unit roundoff;
-// -1 when kMomentMax terms are not enough.
+// -1 when kMomentMax terms are not enough.  For r <= 1, e^r <= 1 + r + r^2
+// stands in for the exponential (a bound, so the count is never too small).
 template <class T>
 __device__ __forceinline__ int moment_count(T r) {
   int K = 0;
-  const T er = exp_t(r);
+  const T er = r <= T(1) ? T(1) + r + r * r : exp_t(r);
   T t = r;
   while (t * er > T(Prec<T>::kUnit) && K < kMomentMax) {
     ++K;
@@ -237,9 +238,24 @@ __device__ __forceinline__ void reduce_moments(const Modes& md, const T* bc, con
       fs = cfma(fs, C<T>{tr, ti}, cm);      // sum (tau)^m mu_m / m!
       gs = cfma(gs, C<T>{-tr, -ti}, cm);    // sum (-tau)^m mu_m / m!
     }
-    const C<T> ef = exp_neg_general<T>(tr, ti, g.hf);
-    const C<T> eg = exp_neg_general<T>(tr, ti, g.hg);
-    const C<T> a = exp_neg_general<T>(tr, ti, g.span);
+    // exp(-tau h) for h = hf, hg: |tau| h <= r, so the series to degree KK >= K
+    // is exact to the unit roundoff (the table holds degrees up to kTaylorMax;
+    // beyond, the library functions); the tile's factor A = exp(-tau (hf + hg)).
+    C<T> ef = {T(0), T(0)}, eg = {T(0), T(0)};
+    if constexpr (KK <= kTaylorMax) {
+#pragma unroll
+      for (int m = KK; m >= 0; --m) {
+        const T c_re = T(md.coef_re[k][m]), c_im = T(md.coef_im[k][m]);
+        ef.re = fma(ef.re, g.hf, c_re);
+        ef.im = fma(ef.im, g.hf, c_im);
+        eg.re = fma(eg.re, g.hg, c_re);
+        eg.im = fma(eg.im, g.hg, c_im);
+      }
+    } else {
+      ef = exp_neg_general<T>(tr, ti, g.hf);
+      eg = exp_neg_general<T>(tr, ti, g.hg);
+    }
+    const C<T> a = cmul(ef, eg);
     const C<T> f = cmul(ef, fs);
     const C<T> gg = cmul(eg, gs);
     T* o = out + k * kAggStride;
@@ -412,7 +428,10 @@ __device__ __forceinline__ void final_fast_body(const Modes& md, const T* dz, co
   }
 }
 
-template <class T, int NM>
+// Two instantiations: moment counts up to kKSteps[2] (the usual case) and the
+// larger ones up to kFastMoments, so that the common kernel keeps fewer
+// registers (its moment arrays are shorter) and runs more waves per SIMD.
+template <class T, int NM, int KMAX>
 __global__ __launch_bounds__(256) void k_wfinal_fast(const void* keys0, const void* keys1,
                                                      const PassInfo* __restrict__ pass,
                                                      const T* __restrict__ bs,
@@ -422,30 +441,36 @@ __global__ __launch_bounds__(256) void k_wfinal_fast(const void* keys0, const vo
                                                      const T* __restrict__ carry,
                                                      const int32_t* __restrict__ tile_k,
                                                      ScanOut<T> out) {
+  constexpr int KMIN = KMAX == kKSteps[2] ? 0 : kKSteps[2] + 1;
   const int lane = threadIdx.x % kWave;
   const int64_t tile = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
   if (tile >= tiles) return;
   const int K = tile_k[tile];
-  if (K < 0 || K > kFastMoments) return;   // k_wfinal's tile
+  if (K < KMIN || K > KMAX) return;   // another kernel's tile
   const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
   const int64_t t0 = tile * kWTile;
   const int64_t base = t0 + lane * kScanChunk;
   T zc[kScanChunk], bc[kScanChunk], dz[kScanChunk], sc[kScanChunk], acc[kScanChunk];
-  uint32_t ic[kScanChunk];
   load_chunk(keys.z, bs, base, P, vec != 0, zc, bc);
-  load_ids(ids, base, P, vec != 0, ic);
   const TileGeo<T> g = tile_geometry(keys.z, t0, P, lane, zc, dz, sc);
 #pragma unroll
   for (int j = 0; j < kScanChunk; ++j) acc[j] = T(0);
   const T* ag = agg + (size_t)tile * NM * kAggStride;
   const T* cr = carry + (size_t)tile * NM * 4;
-  switch (k_class(K)) {
-    case 0: final_fast_body<T, NM, kKSteps[0]>(md, dz, bc, sc, g, lane, ag, cr, acc); break;
-    case 1: final_fast_body<T, NM, kKSteps[1]>(md, dz, bc, sc, g, lane, ag, cr, acc); break;
-    case 2: final_fast_body<T, NM, kKSteps[2]>(md, dz, bc, sc, g, lane, ag, cr, acc); break;
-    case 3: final_fast_body<T, NM, kKSteps[3]>(md, dz, bc, sc, g, lane, ag, cr, acc); break;
-    default: final_fast_body<T, NM, kKSteps[4]>(md, dz, bc, sc, g, lane, ag, cr, acc); break;
+  if constexpr (KMAX == kKSteps[2]) {
+    switch (k_class(K)) {
+      case 0: final_fast_body<T, NM, kKSteps[0]>(md, dz, bc, sc, g, lane, ag, cr, acc); break;
+      case 1: final_fast_body<T, NM, kKSteps[1]>(md, dz, bc, sc, g, lane, ag, cr, acc); break;
+      default: final_fast_body<T, NM, kKSteps[2]>(md, dz, bc, sc, g, lane, ag, cr, acc); break;
+    }
+  } else {
+    if (k_class(K) == 3)
+      final_fast_body<T, NM, kKSteps[3]>(md, dz, bc, sc, g, lane, ag, cr, acc);
+    else
+      final_fast_body<T, NM, kKSteps[4]>(md, dz, bc, sc, g, lane, ag, cr, acc);
   }
+  uint32_t ic[kScanChunk];   // loaded last: not live during the sweeps
+  load_ids(ids, base, P, vec != 0, ic);
   scatter_chunk(out, ic, acc);
 }
 
@@ -541,9 +566,12 @@ hipError_t scan_nm(const Workspace& w, const Modes& md, int64_t P, const T* b,
   tl->mark(s);
   (void)carry_tiles<T>(w, tiles, NM, s);
   tl->mark(s);
-  hipLaunchKernelGGL((k_wfinal_fast<T, NM>), grid, dim3(256), 0, s, w.keys[0], w.keys[1], w.pass,
-                     b, w.ids, P, tiles, vec, md, (const T*)w.agg, (const T*)w.carry, w.tile_k,
-                     out);
+  hipLaunchKernelGGL((k_wfinal_fast<T, NM, kKSteps[2]>), grid, dim3(256), 0, s, w.keys[0],
+                     w.keys[1], w.pass, b, w.ids, P, tiles, vec, md, (const T*)w.agg,
+                     (const T*)w.carry, w.tile_k, out);
+  hipLaunchKernelGGL((k_wfinal_fast<T, NM, kFastMoments>), grid, dim3(256), 0, s, w.keys[0],
+                     w.keys[1], w.pass, b, w.ids, P, tiles, vec, md, (const T*)w.agg,
+                     (const T*)w.carry, w.tile_k, out);
   hipLaunchKernelGGL((k_wfinal<T, NM>), grid, dim3(256), 0, s, w.keys[0], w.keys[1], w.pass, b,
                      w.ids, P, tiles, vec, md, (const T*)w.carry, w.tile_k, out);
   tl->mark(s);

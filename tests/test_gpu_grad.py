@@ -258,6 +258,47 @@ def test_autograd_partial_requirements():
     assert np.max(np.abs(A.grad.cpu().numpy() - ref)) <= 2 * oracle_E(p) * M
 
 
+def test_autograd_reuses_plan_and_workspace():
+    """A second forward of the same shape allocates only its output; forwards
+    that share the cached workspace before their backwards still get their own
+    gradients (the later backward sorts again)."""
+    g0 = np.random.default_rng(16)
+    M, N = 30000, 40000
+    delta = 1e-3
+    say("[gpu] gauss_transform workspace cache")
+    fgt.api._gt_cache.clear()
+    Y = to_dev(g0.random(N), torch.float64)
+    A = to_dev(g0.standard_normal(N), torch.float64)
+    X1 = to_dev(g0.random(M), torch.float64)
+    X2 = to_dev(g0.random(M), torch.float64)
+    G = to_dev(g0.standard_normal(M), torch.float64)
+    u1 = fgt.gauss_transform(X1, Y, A, delta, 6)
+    torch.cuda.synchronize()
+    m0 = torch.cuda.memory_allocated()
+    u2 = fgt.gauss_transform(X2, Y, A, delta, 6)
+    torch.cuda.synchronize()
+    grown = torch.cuda.memory_allocated() - m0
+    assert grown <= ((M * 8 + 511) // 512) * 512, grown
+    # interleaved: forward 1, forward 2 (same cached workspace), backward 1, backward 2
+    x1 = X1.clone().requires_grad_()
+    x2 = X2.clone().requires_grad_()
+    a1 = A.clone().requires_grad_()
+    a2 = A.clone().requires_grad_()
+    v1 = fgt.gauss_transform(x1, Y, a1, delta, 6)
+    v2 = fgt.gauss_transform(x2, Y, a2, delta, 6)
+    (v1 * G).sum().backward()
+    (v2 * G).sum().backward()
+    p = fgt.plan(delta, 6)
+    for xs, xg, ag in ((X1, x1.grad, a1.grad), (X2, x2.grad, a2.grad)):
+        da, dx, _, _ = fgt.backward(xs, Y, A, G, p)
+        np.testing.assert_allclose(xg.cpu().numpy(), dx.cpu().numpy(), rtol=0,
+                                   atol=1e-12 * float(dx.abs().max()))
+        np.testing.assert_allclose(ag.cpu().numpy(), da.cpu().numpy(), rtol=0,
+                                   atol=1e-12 * float(da.abs().max()))
+    np.testing.assert_array_equal(u1.cpu().numpy(), v1.detach().cpu().numpy())
+    np.testing.assert_array_equal(u2.cpu().numpy(), v2.detach().cpu().numpy())
+
+
 def test_gradcheck_tiny():
     g0 = np.random.default_rng(15)
     say("[gpu] torch.autograd.gradcheck, 11 digits")
