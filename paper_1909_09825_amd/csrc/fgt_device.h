@@ -49,6 +49,38 @@ __device__ __forceinline__ T shfl_down(T v, int o) { return __shfl_down(v, (unsi
 template <class T>
 __device__ __forceinline__ T shfl_xor(T v, int o) { return __shfl_xor(v, o, kWave); }
 
+// Inclusive sum over the wave's lanes in registers (DPP): Hillis-Steele steps
+// of 1, 2, 4 and 8 lanes inside each row of 16 (row_shr), then the totals of
+// rows 0 and 2 into rows 1 and 3 (row_bcast:15) and of rows 0-1 into rows
+// 2-3 (row_bcast:31).  A lane whose source is outside its row, or whose row
+// is masked out, receives 0 (the `old` operand, bound_ctrl off), so it adds
+// nothing.  64-bit values move as two 32-bit halves.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+template <class T>
+__device__ __forceinline__ T wave_inclusive_sum(T v) {
+  v += dpp_move<0x111, 0xf>(v);   // row_shr:1
+  v += dpp_move<0x112, 0xf>(v);   // row_shr:2
+  v += dpp_move<0x114, 0xf>(v);   // row_shr:4
+  v += dpp_move<0x118, 0xf>(v);   // row_shr:8
+  v += dpp_move<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+// The sum over the whole wave, in every lane.
+template <class T>
+__device__ __forceinline__ T wave_total(T v) {
+  return __shfl(wave_inclusive_sum(v), kWave - 1, kWave);
+}
+
 template <class T> struct Prec;
 template <> struct Prec<double> { static constexpr double kUnit = 1.1102230246251565e-16; };  // 2^-53
 template <> struct Prec<float> { static constexpr double kUnit = 5.9604644775390625e-08; };    // 2^-24

@@ -221,12 +221,9 @@ __device__ __forceinline__ void reduce_moments(const Modes& md, const T* bc, con
       mu[m] += pw;
     }
   }
-  // Butterfly sums: every lane ends with the same, order-fixed totals.
+  // Wave totals (the same, order-fixed sum in every lane).
 #pragma unroll
-  for (int o = kWave / 2; o >= 1; o >>= 1) {
-#pragma unroll
-    for (int m = 0; m <= KK; ++m) mu[m] += shfl_xor(mu[m], o);
-  }
+  for (int m = 0; m <= KK; ++m) mu[m] = wave_total(mu[m]);
   if (lane < NM) {
     const int k = lane;
     const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
@@ -386,12 +383,7 @@ __device__ __forceinline__ void final_fast_body(const Modes& md, const T* dz, co
         nu += pw[j];
         pw[j] *= sc[j];
       }
-      T inc = nu;
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const T v = shfl_up(inc, o);
-        if (lane >= o) inc += v;
-      }
+      const T inc = wave_inclusive_sum(nu);
       const T tot = __shfl(inc, kWave - 1, kWave);
       const T exc = shfl_up(inc, 1);
       const T f = T(kInvFact.v[m]);
