@@ -233,11 +233,6 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
   const DigitLayout L = digit_layout<T>(range, res, cd);
   const uint32_t mask = (1u << L.bits) - 1u;
 
-  // Run-length counting per digit: constant high digits (common for
-  // coordinates of one sign and exponent range) cost one LDS atomic per run.
-  uint32_t cur[D], cnt[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) { cur[d] = 0u; cnt[d] = 0u; }
   RangeAcc acc;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   constexpr int kBatch = 8;   // loads issued together before they are used
@@ -258,18 +253,10 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
       for (int d = 0; d < D; ++d) {
         if (d >= L.passes) continue;
         const uint32_t dig = (uint32_t)(k >> (L.lo_bit + L.bits * d)) & mask;
-        if (cnt[d] != 0u && dig != cur[d]) {
-          atomicAdd(&h[d * kSortRadix + cur[d]], cnt[d]);
-          cnt[d] = 0u;
-        }
-        cur[d] = dig;
-        ++cnt[d];
+        atomicAdd(&h[d * kSortRadix + dig], 1u);
       }
     }
   }
-#pragma unroll
-  for (int d = 0; d < D; ++d)
-    if (cnt[d]) atomicAdd(&h[d * kSortRadix + cur[d]], cnt[d]);
   if (kGatherRange) acc.publish(range, status);
   __syncthreads();
   for (int i = threadIdx.x; i < D * kSortRadix; i += blockDim.x)
