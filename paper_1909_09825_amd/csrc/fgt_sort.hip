@@ -367,8 +367,10 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   const int dbits = pass->bits;          // 8 or 9 for the whole sort
   const int ndig = 1 << dbits;
   if (!run) {
-    // Nothing moves; still clear the other look-back buffer for the next pass.
-    if (tid < ndig)
+    // Nothing moves; still clear the other look-back buffer for the next pass
+    // that runs (none after the last: the next sort's first pass starts from
+    // the buffer k_clear zeroes, and each pass clears the one after it).
+    if (d < pass->last_pass && tid < ndig)
       for (int64_t t = blockIdx.x; t * kSortTile < P; t += gridDim.x)
         lb_next[(size_t)t * kSortRadix + tid] = 0ull;
     return;
