@@ -280,6 +280,37 @@ int fgt_batch_eval(fgt_batch_t plan, const void* x, const void* y, const void* a
                    void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * fgt_batch_sorted -- the sort step of a batch (Section 4's ascending order of
+ * each transform's merged sources and targets) as the last fgt_batch_eval on
+ * `ws` left it, copied out on `stream`.
+ *   codes [P] uint32 device array (may be null), P = sum_b (M_b + N_b): at
+ *         sorted position p, the point's code: j for source row j (y[j],
+ *         alpha rows), SN + i for target row i (x[i]), SN = sum_b N_b.
+ *         Transform b holds positions [base_b, base_b + M_b + N_b), base_b
+ *         the sum of M + N over the transforms before it.
+ *   z     [P] double device array (may be null): the point's coordinate as
+ *         given (unscaled), bit for bit.
+ *   resolution  host double (may be null): the sort resolution s in scaled
+ *         units (coordinate / sqrt(delta_b)).
+ * Order within transform b: ascending in the key
+ *   q = trunc(clamp((z / sqrt(delta_b) - lo_b) * 2^62 / (hi_b - lo_b), 0, 2^62)),
+ * lo_b, hi_b the smallest and largest scaled coordinate (each product and
+ * difference rounded in FP64 as written), with the key bits below
+ * 8 floor(L / 8) ignored, L = floor(log2(s 2^62 / (hi_b - lo_b))) clamped to
+ * [0, 62]; equal (truncated) keys keep the merged order [sources; targets].
+ * The key never decreases as the coordinate grows, so two points out of
+ * coordinate order have equal keys above those bits: they lie closer than
+ * s sqrt(delta_b) plus the rounding of the key's arithmetic (at most 2^11 + 1
+ * key units, a key unit being (hi_b - lo_b) sqrt(delta_b) / 2^62, plus two
+ * units in the last place of the larger coordinate).
+ * ws must hold a completed fgt_batch_eval of this plan: otherwise the values
+ * are unspecified (no access outside ws, codes and z).
+ * Errors: FGT_EINVAL (null plan or ws, short or misaligned workspace), FGT_EDEVICE.
+ */
+int fgt_batch_sorted(fgt_batch_t plan, const void* ws, size_t ws_bytes, uint32_t* codes, void* z,
+                     double* resolution, hipStream_t stream);
+
+/*
  * Autotuning.  Two choices shape the batched kernels: the points each lane
  * runs per column in the scan (`chunk`: 8 or 16) and the size the sort aims
  * for when it splits a transform into LDS-sorted buckets (`bucket_points`:

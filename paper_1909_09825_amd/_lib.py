@@ -70,6 +70,8 @@ def load() -> ctypes.CDLL:
     lib.fgt_batch_info.restype = c_int
     lib.fgt_batch_eval.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.fgt_batch_eval.restype = c_int
+    lib.fgt_batch_sorted.argtypes = [vp, vp, ctypes.c_size_t, vp, vp, dp, vp]
+    lib.fgt_batch_sorted.restype = c_int
     lib.fgt_batch_tune.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.c_char_p]
     lib.fgt_batch_tune.restype = c_int
     lib.fgt_batch_config.argtypes = [vp, ip, ip]

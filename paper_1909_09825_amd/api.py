@@ -486,6 +486,27 @@ def eval_batch(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor, bp: BatchP
     return out
 
 
+def batch_sorted(bp: BatchPlan, ws: torch.Tensor):
+    """The sort step of the last eval_batch on `ws` (fgt_batch_sorted): (codes, z, resolution).
+
+    codes[p] (int64) is source row j (< SN) or SN + target row i at sorted
+    position p, transforms one after another; z[p] the coordinate as given;
+    resolution the sort resolution in scaled units (coordinate / sqrt(delta)).
+    """
+    need = bp.workspace_size()
+    if ws.numel() * ws.element_size() < need or not ws.is_contiguous() or not ws.is_cuda:
+        raise ValueError(f"workspace must be a contiguous device tensor of >= {need} bytes")
+    dev = ws.device
+    P = bp.M + bp.N
+    codes = torch.empty(P, dtype=torch.int32, device=dev)
+    z = torch.empty(P, dtype=torch.float64, device=dev)
+    res = ctypes.c_double()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    check(bp._lib.fgt_batch_sorted(bp.handle, ws.data_ptr(), need, codes.data_ptr(), z.data_ptr(),
+                                   ctypes.byref(res), stream), "fgt_batch_sorted")
+    return codes.long() & 0xFFFFFFFF, z, res.value
+
+
 def batch_workspace(bp: BatchPlan, device) -> torch.Tensor:
     return torch.empty(max(bp.workspace_size(), 1), dtype=torch.uint8, device=device)
 

@@ -839,6 +839,17 @@ int fgt_batch_eval(fgt_batch_t plan, const void* x, const void* y, const void* a
   return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
 }
 
+int fgt_batch_sorted(fgt_batch_t plan, const void* ws, size_t ws_bytes, uint32_t* codes, void* z,
+                     double* resolution, hipStream_t stream) {
+  if (!plan || !ws) return FGT_EINVAL;
+  if (((uintptr_t)ws & 255u) != 0) return FGT_EINVAL;
+  const fgt::BatchWork w = fgt::batch_layout(const_cast<void*>(ws), plan->dims);
+  if (ws_bytes < w.total) return FGT_EINVAL;
+  if (resolution) *resolution = plan->s_allow;
+  const hipError_t e = fgt::batch_sorted_copy(plan->dims, w, codes, (double*)z, stream);
+  return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
+}
+
 int fgt_batch_tune(fgt_batch_t plan, const void* x, const void* y, const void* alpha, void* u,
                    void* ws, size_t ws_bytes, hipStream_t stream, const char* cache_path) {
   if (!plan) return FGT_EINVAL;

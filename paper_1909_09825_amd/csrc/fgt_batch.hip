@@ -866,6 +866,18 @@ __global__ void k_clear_words(uint32_t* __restrict__ p, int n) {
   if (i < n) p[i] = 0u;
 }
 
+// Sorted codes (transform-start flag cleared) and coordinates of a batch.
+__global__ __launch_bounds__(256) void k_batch_sorted(const uint32_t* __restrict__ ids,
+                                                      const double* __restrict__ zs, int64_t P,
+                                                      uint32_t* __restrict__ codes,
+                                                      double* __restrict__ z) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += stride) {
+    if (codes) codes[p] = ids[p] & ~kSegStart;
+    if (z) z[p] = zs[p];
+  }
+}
+
 }  // namespace
 
 BatchWork batch_layout(void* base, const BatchDims& d) {
@@ -948,6 +960,16 @@ hipError_t batch_eval_launch(const BatchDims& d, const BatchTables& t, const Mod
     case 7: return batch_scan_chunk<7>(chunk, d, md, ne_base, ne_scale, alpha, u, w, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t batch_sorted_copy(const BatchDims& d, const BatchWork& w, uint32_t* codes, double* z,
+                             hipStream_t s) {
+  if (d.P == 0 || (!codes && !z)) return hipSuccess;
+  int64_t blocks = (d.P + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_batch_sorted, dim3((unsigned)blocks), dim3(256), 0, s, w.ids, w.zs, d.P,
+                     codes, z);
+  return hipGetLastError();
 }
 
 }  // namespace fgt

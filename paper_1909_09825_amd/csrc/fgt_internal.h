@@ -451,4 +451,8 @@ hipError_t batch_eval_launch(const BatchDims& d, const BatchTables& t, const Mod
                              double s_allow, int chunk, const double* x, const double* y,
                              const double* alpha, double* u, const BatchWork& w, hipStream_t s);
 
+// The sorted codes (kSegStart cleared) and coordinates a batch left in w.
+hipError_t batch_sorted_copy(const BatchDims& d, const BatchWork& w, uint32_t* codes, double* z,
+                             hipStream_t s);
+
 }  // namespace fgt

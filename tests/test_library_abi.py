@@ -186,6 +186,7 @@ def test_batch_plan_validation():
     assert lib.fgt_batch_plan(3, None, 6, fgt.FGT_F64, _i64p(xo), _i64p(yo), 4,
                               ctypes.byref(h)) == fgt.FGT_EINVAL
     assert lib.fgt_batch_eval(None, None, None, None, None, None, 0, None) == fgt.FGT_EINVAL
+    assert lib.fgt_batch_sorted(None, None, 0, None, None, None, None) == fgt.FGT_EINVAL
     assert lib.fgt_batch_workspace_size(None) == 0
     lib.fgt_batch_destroy(None)
 
