@@ -376,7 +376,7 @@ def bench_clustered(args, fgt, W, torch, np, dev):
                      "ms_per_transform": round(wall, 5), "ms_median_event": round(med, 5),
                      "value": P * p.n_modes / (wall * 1e-3), "unit": "point-modes/s",
                      "phase_ms": {k: round(v / calls, 5) for k, v in phases.items()},
-                     "scan": scan_row(phases, calls, 2 * esz * P + (esz + 4) * pr.M)})
+                     "scan": scan_row(phases, calls, (esz + 4) * P + esz * (pr.N + pr.M))})
         del X, Y, A, ws, u
     return {"workload": ("N = 2^24 sources from a 64-component Gaussian mixture (centres U[0,1), "
                          "sigma log-uniform in [1e-5, 1e-2]), M = 2^22 targets U[0,1), "
@@ -492,19 +492,20 @@ def main():
     dominant = max(groups, key=groups.get)
     # Algorithmic bytes per launch.  First pass: read the coordinate, write key
     # and index; middle passes: read and write key and index; last pass: read
-    # key and index, gather alpha for the sources, write key, strength, slot.
+    # key and index, write coordinate and index.  The tile reduce reads the
+    # coordinates and merged ids, gathers alpha for the sources and writes the
+    # sorted strengths; the final kernel reads coordinates, strengths and ids
+    # and scatters u.
     first = P * (esz + esz + 4)
     middle = P * 2 * (esz + 4)
-    last = P * (esz + 4) + N * esz + P * (2 * esz + 4)
     if n_run <= 1:
-        sort_bytes = P * esz + N * esz + P * (2 * esz + 4)
+        sort_bytes = P * (2 * esz + 4)
     else:
-        sort_bytes = (first + (n_run - 2) * middle + last) / n_run
-    scan_read = P * (2 * esz)                        # coordinates and strengths
+        sort_bytes = (first + (n_run - 1) * middle) / n_run
     alg = {
         "k_onesweep": sort_bytes,
-        "k_final": scan_read + P * 4 + M * esz,      # + ids, + u scattered
-        "k_reduce": scan_read,
+        "k_final": P * (2 * esz + 4) + M * esz,
+        "k_reduce": P * (esz + 4) + N * esz + P * esz,
     }
     launches = {"k_onesweep": max(n_run, 1), "k_final": 1, "k_reduce": 1}
     counter_name = {"k_onesweep": "k_onesweep", "k_final": "k_wfinal_fast", "k_reduce": "k_wreduce"}
@@ -545,7 +546,9 @@ def main():
             "transforms_per_s": 1e3 / ms_step,
             "phase_ms_per_step": {k: round(v, 5) for k, v in per_step.items()},
             "kernels": kernels,
-            "scan": scan_row(phases, calls, P * 2 * esz + M * (esz + 4)),
+            # one pass over the sorted points: coordinates and ids read once,
+            # alpha read once, u written once
+            "scan": scan_row(phases, calls, P * (esz + 4) + N * esz + M * esz),
         },
         "roofline": {
             "kernel": dom,

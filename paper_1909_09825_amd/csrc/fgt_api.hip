@@ -223,16 +223,14 @@ hipError_t forward(const fgt_plan_s* plan, const Workspace& w, const void* x, in
                    const void* y, const void* alpha, int64_t N, void* u, bool sort,
                    hipStream_t s, Timeline* tl) {
   const int64_t P = M + N;
-  hipError_t e = hipSuccess;
   if (sort) {
-    e = sort_points<T>(w, (const T*)x, M, (const T*)y, (const T*)alpha, N, plan->modes.sort,
-                       s, tl);
-  } else {
-    e = gather_strengths<T>(w, P, 0u, (uint32_t)N, (const T*)alpha, (T*)w.b, s);
+    const hipError_t e =
+        sort_points<T>(w, (const T*)x, M, (const T*)y, N, plan->modes.sort, s, tl);
+    if (e != hipSuccess) return e;
   }
-  if (e != hipSuccess) return e;
+  // The scan's tile reduce gathers alpha into sorted order (ids below N are sources).
   const ScanOut<T> out{(T*)u, nullptr, nullptr, (uint32_t)N, (uint32_t)M};
-  return scan_points<T>(w, plan->modes, P, (const T*)w.b, out, s, tl);
+  return scan_points<T>(w, plan->modes, P, nullptr, (const T*)alpha, (uint32_t)N, out, s, tl);
 }
 
 // Gradients of L = sum_i g_i u_i (see fgt_backward): sort if asked, then the
@@ -243,8 +241,9 @@ hipError_t backward(const fgt_plan_s* plan, const Workspace& w, const void* x, i
                     void* dx, void* dy, void* ddelta, bool sort, hipStream_t s) {
   if (sort) {
     Timeline none;
-    const hipError_t e = sort_points<T>(w, (const T*)x, M, (const T*)y, (const T*)alpha, N,
-                                        plan->modes.sort, s, &none);
+    hipError_t e = sort_points<T>(w, (const T*)x, M, (const T*)y, N, plan->modes.sort, s, &none);
+    if (e == hipSuccess)
+      e = gather_strengths<T>(w, M + N, 0u, (uint32_t)N, (const T*)alpha, (T*)w.b, s);
     if (e != hipSuccess) return e;
   }
   return adjoint_points<T>(w, plan->modes, M, N, (const T*)g, (T*)dx, (T*)dalpha, (T*)dy,
@@ -429,12 +428,16 @@ int fgt_sort(fgt_plan_t plan, const void* x, int64_t M, const void* y, const voi
   fgt::Timeline none;
   hipError_t e;
   if (f64) {
-    e = fgt::sort_points<double>(w, (const double*)x, M, (const double*)y, (const double*)alpha, N,
-                                 res, stream, &none);
+    e = fgt::sort_points<double>(w, (const double*)x, M, (const double*)y, N, res, stream, &none);
+    if (e == hipSuccess && alpha)
+      e = fgt::gather_strengths<double>(w, P, 0u, (uint32_t)N, (const double*)alpha,
+                                        (double*)w.b, stream);
     if (e == hipSuccess && (perm || z)) e = fgt::copy_sorted<double>(w, P, perm, (double*)z, stream);
   } else {
-    e = fgt::sort_points<float>(w, (const float*)x, M, (const float*)y, (const float*)alpha, N, res,
-                                stream, &none);
+    e = fgt::sort_points<float>(w, (const float*)x, M, (const float*)y, N, res, stream, &none);
+    if (e == hipSuccess && alpha)
+      e = fgt::gather_strengths<float>(w, P, 0u, (uint32_t)N, (const float*)alpha, (float*)w.b,
+                                       stream);
     if (e == hipSuccess && (perm || z)) e = fgt::copy_sorted<float>(w, P, perm, (float*)z, stream);
   }
   return e == hipSuccess ? FGT_OK : FGT_EDEVICE;
@@ -477,23 +480,24 @@ int fgt_eval_self(fgt_plan_t plan, const void* x, int64_t N, const void* alpha, 
   hipError_t e;
   // Every point is a source (strength alpha) and a target (output u): merged ids in [0, N).
   if (f64) {
-    e = (flags & FGT_PRESORTED)
-            ? fgt::presorted_points<double>(w, (const double*)x, (const double*)alpha, N, stream)
-            : fgt::sort_points<double>(w, nullptr, 0, (const double*)x, (const double*)alpha, N,
-                                       plan->modes.sort, stream, &none);
+    // Presorted: the strengths are read in place; sorted here: the tile reduce gathers them.
+    const bool pre = (flags & FGT_PRESORTED) != 0;
+    e = pre ? fgt::presorted_points<double>(w, (const double*)x, (const double*)alpha, N, stream)
+            : fgt::sort_points<double>(w, nullptr, 0, (const double*)x, N, plan->modes.sort, stream,
+                                       &none);
     if (e == hipSuccess)
-      e = fgt::scan_points<double>(w, plan->modes, N,
-                                   (flags & FGT_PRESORTED) ? (const double*)alpha : (const double*)w.b,
+      e = fgt::scan_points<double>(w, plan->modes, N, pre ? (const double*)alpha : nullptr,
+                                   pre ? nullptr : (const double*)alpha, (uint32_t)N,
                                    fgt::ScanOut<double>{(double*)u, nullptr, nullptr, 0u, (uint32_t)N},
                                    stream, &none);
   } else {
-    e = (flags & FGT_PRESORTED)
-            ? fgt::presorted_points<float>(w, (const float*)x, (const float*)alpha, N, stream)
-            : fgt::sort_points<float>(w, nullptr, 0, (const float*)x, (const float*)alpha, N,
-                                      plan->modes.sort, stream, &none);
+    const bool pre = (flags & FGT_PRESORTED) != 0;
+    e = pre ? fgt::presorted_points<float>(w, (const float*)x, (const float*)alpha, N, stream)
+            : fgt::sort_points<float>(w, nullptr, 0, (const float*)x, N, plan->modes.sort, stream,
+                                      &none);
     if (e == hipSuccess)
-      e = fgt::scan_points<float>(w, plan->modes, N,
-                                   (flags & FGT_PRESORTED) ? (const float*)alpha : (const float*)w.b,
+      e = fgt::scan_points<float>(w, plan->modes, N, pre ? (const float*)alpha : nullptr,
+                                  pre ? nullptr : (const float*)alpha, (uint32_t)N,
                                   fgt::ScanOut<float>{(float*)u, nullptr, nullptr, 0u, (uint32_t)N},
                                   stream, &none);
   }

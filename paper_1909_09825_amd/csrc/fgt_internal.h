@@ -330,13 +330,15 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes);
 // zero widths sort every digit, a zero code_tol keeps IEEE keys wherever the
 // grid code would move a point.
 template <class T>
-hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, const T* alpha,
-                       int64_t N, const SortRes& res, hipStream_t s, Timeline* tl);
-// Scan of strengths `b` ([P], sorted order) over the sorted coordinates; writes what
-// `out` asks for.
+hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, int64_t N,
+                       const SortRes& res, hipStream_t s, Timeline* tl);
+// Scan over the sorted coordinates; writes what `out` asks for.  The strengths
+// in sorted order are `b` ([P]) when `src` is null; otherwise the tile reduce
+// gathers them, b_p = src[id_p] for id_p < n_src and 0 else, and stores them
+// to w.b for the kernels after it.
 template <class T>
-hipError_t scan_points(const Workspace& w, const Modes& m, int64_t P, const T* b,
-                       const ScanOut<T>& out, hipStream_t s, Timeline* tl);
+hipError_t scan_points(const Workspace& w, const Modes& m, int64_t P, const T* b, const T* src,
+                       uint32_t n_src, const ScanOut<T>& out, hipStream_t s, Timeline* tl);
 // b[p] = wts[id_p - lo] if that index is below n, else 0.
 template <class T>
 hipError_t gather_strengths(const Workspace& w, int64_t P, uint32_t lo, uint32_t n, const T* wts,

@@ -119,6 +119,53 @@ __device__ __forceinline__ void load_ids(const uint32_t* __restrict__ ids, int64
   }
 }
 
+// The tile reduce's gather of the strengths in sorted order: the lane's
+// coordinates and merged ids, then b_j = src[id_j] for a source (id_j < n) and
+// 0 for a target, stored to b for the kernels after the reduce.  The random
+// reads overlap the other waves' streams, which a separate gather pass (or
+// the last radix pass) would leave idle.
+template <class T>
+__device__ __forceinline__ void load_gather(const T* __restrict__ z,
+                                            const uint32_t* __restrict__ ids,
+                                            const T* __restrict__ src, uint32_t n,
+                                            T* __restrict__ b, int64_t base, int64_t P, bool vec,
+                                            T* zc, T* bc) {
+  constexpr int C = kScanChunk;
+  uint32_t ic[C];
+  load_ids(ids, base, P, vec, ic);   // kNoSlot past the end
+  const bool full = vec && base + C <= P;
+  typedef T V __attribute__((ext_vector_type(16 / sizeof(T))));
+  constexpr int L = 16 / sizeof(T);
+  if (full) {
+    const V* pz = reinterpret_cast<const V*>(z + base);
+#pragma unroll
+    for (int q = 0; q < C / L; ++q) {
+      const V vz = pz[q];
+#pragma unroll
+      for (int i = 0; i < L; ++i) zc[q * L + i] = vz[i];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < C; ++j) zc[j] = base + j < P ? z[base + j] : T(0);
+  }
+#pragma unroll
+  for (int j = 0; j < C; ++j) bc[j] = ic[j] < n ? src[ic[j]] : T(0);
+  if (full) {
+    V* pb = reinterpret_cast<V*>(b + base);
+#pragma unroll
+    for (int q = 0; q < C / L; ++q) {
+      V v;
+#pragma unroll
+      for (int i = 0; i < L; ++i) v[i] = bc[q * L + i];
+      pb[q] = v;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      if (base + j < P) b[base + j] = bc[j];
+  }
+}
+
 // Geometry of a wave's tile.  zs: the point before the lane's chunk (the
 // tile's previous point for lane 0); ze: the lane's last point (the tile's
 // last point for a lane past the end); dz, sc: gaps and offsets from the tile
@@ -264,10 +311,15 @@ __device__ __forceinline__ void reduce_moments(const Modes& md, const T* bc, con
   }
 }
 
+// Strengths: read from bs, or (src set) gathered from src by merged id and
+// stored to b_store.
 template <class T, int NM>
 __global__ __launch_bounds__(256) void k_wreduce(const void* keys0, const void* keys1,
                                                  const PassInfo* __restrict__ pass,
-                                                 const T* __restrict__ bs, int64_t P,
+                                                 const T* __restrict__ bs,
+                                                 const T* __restrict__ src, uint32_t n_src,
+                                                 const uint32_t* __restrict__ ids,
+                                                 T* __restrict__ b_store, int64_t P,
                                                  int64_t tiles, int vec, Modes md,
                                                  T* __restrict__ agg,
                                                  int32_t* __restrict__ tile_k) {
@@ -277,7 +329,10 @@ __global__ __launch_bounds__(256) void k_wreduce(const void* keys0, const void* 
   if (tile >= tiles) return;
   const int64_t t0 = tile * kWTile;
   T zc[kScanChunk], bc[kScanChunk], dz[kScanChunk], sc[kScanChunk];
-  load_chunk(keys.z, bs, t0 + lane * kScanChunk, P, vec != 0, zc, bc);
+  if (src)
+    load_gather(keys.z, ids, src, n_src, b_store, t0 + lane * kScanChunk, P, vec != 0, zc, bc);
+  else
+    load_chunk(keys.z, bs, t0 + lane * kScanChunk, P, vec != 0, zc, bc);
   const TileGeo<T> g = tile_geometry(keys.z, t0, P, lane, zc, dz, sc);
   const int K = moment_count(T(md.tau_abs_max) * (g.hf > g.hg ? g.hf : g.hg));
   if (lane == 0) tile_k[tile] = K;
@@ -547,14 +602,17 @@ hipError_t carry_tiles(const Workspace& w, int64_t tiles, int nq, hipStream_t s)
 inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 template <class T, int NM>
-hipError_t scan_nm(const Workspace& w, const Modes& md, int64_t P, const T* b,
-                   const ScanOut<T>& out, hipStream_t s, Timeline* tl) {
+hipError_t scan_nm(const Workspace& w, const Modes& md, int64_t P, const T* b_in, const T* src,
+                   uint32_t n_src, const ScanOut<T>& out, hipStream_t s, Timeline* tl) {
   const int64_t tiles = (P + kWTile - 1) / kWTile;
   const dim3 grid((unsigned)((tiles + 3) / 4));
+  // With src the reduce stores the gathered strengths to w.b for the later kernels.
+  const T* b = src ? (const T*)w.b : b_in;
   const int vec = aligned16(w.keys[0]) && aligned16(w.keys[1]) && aligned16(b) &&
                   aligned16(w.ids);
-  hipLaunchKernelGGL((k_wreduce<T, NM>), grid, dim3(256), 0, s, w.keys[0], w.keys[1], w.pass, b,
-                     P, tiles, vec, md, (T*)w.agg, w.tile_k);
+  hipLaunchKernelGGL((k_wreduce<T, NM>), grid, dim3(256), 0, s, w.keys[0], w.keys[1], w.pass,
+                     src ? nullptr : b, src, n_src, (const uint32_t*)w.ids, (T*)w.b, P, tiles, vec,
+                     md, (T*)w.agg, w.tile_k);
   tl->mark(s);
   (void)carry_tiles<T>(w, tiles, NM, s);
   tl->mark(s);
@@ -585,17 +643,17 @@ __global__ __launch_bounds__(256) void k_gather(const uint32_t* __restrict__ ids
 }  // namespace
 
 template <class T>
-hipError_t scan_points(const Workspace& w, const Modes& md, int64_t P, const T* b,
-                       const ScanOut<T>& out, hipStream_t s, Timeline* tl) {
+hipError_t scan_points(const Workspace& w, const Modes& md, int64_t P, const T* b, const T* src,
+                       uint32_t n_src, const ScanOut<T>& out, hipStream_t s, Timeline* tl) {
   if (!out.val || out.der) return hipErrorInvalidValue;   // the adjoint has its own kernels
   switch (md.n) {
-    case 1: return scan_nm<T, 1>(w, md, P, b, out, s, tl);
-    case 2: return scan_nm<T, 2>(w, md, P, b, out, s, tl);
-    case 3: return scan_nm<T, 3>(w, md, P, b, out, s, tl);
-    case 4: return scan_nm<T, 4>(w, md, P, b, out, s, tl);
-    case 5: return scan_nm<T, 5>(w, md, P, b, out, s, tl);
-    case 6: return scan_nm<T, 6>(w, md, P, b, out, s, tl);
-    case 7: return scan_nm<T, 7>(w, md, P, b, out, s, tl);
+    case 1: return scan_nm<T, 1>(w, md, P, b, src, n_src, out, s, tl);
+    case 2: return scan_nm<T, 2>(w, md, P, b, src, n_src, out, s, tl);
+    case 3: return scan_nm<T, 3>(w, md, P, b, src, n_src, out, s, tl);
+    case 4: return scan_nm<T, 4>(w, md, P, b, src, n_src, out, s, tl);
+    case 5: return scan_nm<T, 5>(w, md, P, b, src, n_src, out, s, tl);
+    case 6: return scan_nm<T, 6>(w, md, P, b, src, n_src, out, s, tl);
+    case 7: return scan_nm<T, 7>(w, md, P, b, src, n_src, out, s, tl);
     default: return hipErrorInvalidValue;
   }
 }
@@ -620,9 +678,11 @@ hipError_t fill_zero(T* u, int64_t n, hipStream_t s) {
 }
 
 template hipError_t scan_points<double>(const Workspace&, const Modes&, int64_t, const double*,
-                                        const ScanOut<double>&, hipStream_t, Timeline*);
+                                        const double*, uint32_t, const ScanOut<double>&,
+                                        hipStream_t, Timeline*);
 template hipError_t scan_points<float>(const Workspace&, const Modes&, int64_t, const float*,
-                                       const ScanOut<float>&, hipStream_t, Timeline*);
+                                       const float*, uint32_t, const ScanOut<float>&, hipStream_t,
+                                       Timeline*);
 template hipError_t gather_strengths<double>(const Workspace&, int64_t, uint32_t, uint32_t,
                                              const double*, double*, hipStream_t);
 template hipError_t gather_strengths<float>(const Workspace&, int64_t, uint32_t, uint32_t,

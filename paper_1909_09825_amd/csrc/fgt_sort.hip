@@ -22,8 +22,8 @@
 //                 tile offsets by decoupled look-back (Merrill & Garland),
 //                 scatter staged through LDS so writes are coalesced runs.
 //                 Passes whose digit is constant return at once.  The last
-//                 pass stores the decoded coordinates, the final ids and the
-//                 strengths (alpha gathered once).
+//                 pass stores the decoded coordinates and the final ids (the
+//                 scan's tile reduce gathers the strengths by id).
 #include "fgt_internal.h"
 
 namespace fgt {
@@ -346,8 +346,8 @@ __global__ __launch_bounds__(512) void k_plan(const uint32_t* __restrict__ hist,
 
 template <class T>
 __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
-    int d, const T* __restrict__ x, const T* __restrict__ y, const T* __restrict__ alpha, int64_t N,
-    int64_t P, void* keys0, void* keys1, uint32_t* idx0, uint32_t* idx1, T* __restrict__ b_out,
+    int d, const T* __restrict__ x, const T* __restrict__ y, int64_t N,
+    int64_t P, void* keys0, void* keys1, uint32_t* idx0, uint32_t* idx1,
     uint32_t* __restrict__ ids_out,
     const uint32_t* __restrict__ dig_off, const PassInfo* __restrict__ pass,
     uint32_t* __restrict__ tile_ctr, uint64_t* lb_cur, uint64_t* lb_next,
@@ -601,20 +601,17 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     if (base + i * kWave + lane < P && pos[i] < (uint32_t)kSortTile) sid[pos[i]] = id[i];
   __syncthreads();
   // The last pass writes the final permutation to its own array, which the
-  // scans keep using, and the strength of each sorted point (alpha gathered
-  // here, once).
+  // scans keep using.
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int j = tid + r * kSortThreads;
     if (j >= nvalid || outpos[r] == 0xffffffffu) continue;
     const uint32_t out = outpos[r];
     const uint32_t id = sid[j];
-    if (last) {
-      b_out[out] = (alpha && (int64_t)id < N) ? alpha[id] : T(0);
+    if (last)
       ids_out[out] = id;
-    } else {
+    else
       iout[out] = id;
-    }
   }
 }
 
@@ -692,8 +689,8 @@ template hipError_t presorted_points<float>(const Workspace&, const float*, cons
                                             hipStream_t);
 
 template <class T>
-hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, const T* alpha,
-                       int64_t N, const SortRes& res, hipStream_t s, Timeline* tl) {
+hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, int64_t N,
+                       const SortRes& res, hipStream_t s, Timeline* tl) {
   constexpr int D = KeyOf<T>::kDigits;
   const int64_t P = M + N;
   tl->mark(s);
@@ -714,7 +711,7 @@ hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, co
   tl->mark(s);
   for (int d = 0; d < D; ++d) {
     hipLaunchKernelGGL(k_onesweep<T>, dim3((unsigned)w.sort_tiles), dim3(kSortThreads), 0, s, d, x,
-                       y, alpha, N, P, w.keys[0], w.keys[1], w.idx[0], w.idx[1], (T*)w.b, w.ids,
+                       y, N, P, w.keys[0], w.keys[1], w.idx[0], w.idx[1], w.ids,
                        w.dig_off, w.pass,
                        w.tile_ctr, w.lookback[d & 1], w.lookback[(d + 1) & 1], w.status);
     tl->mark(s);
@@ -723,10 +720,8 @@ hipError_t sort_points(const Workspace& w, const T* x, int64_t M, const T* y, co
 }
 
 template hipError_t sort_points<double>(const Workspace&, const double*, int64_t, const double*,
-                                        const double*, int64_t, const SortRes&, hipStream_t,
-                                        Timeline*);
+                                        int64_t, const SortRes&, hipStream_t, Timeline*);
 template hipError_t sort_points<float>(const Workspace&, const float*, int64_t, const float*,
-                                       const float*, int64_t, const SortRes&, hipStream_t,
-                                       Timeline*);
+                                       int64_t, const SortRes&, hipStream_t, Timeline*);
 
 }  // namespace fgt
