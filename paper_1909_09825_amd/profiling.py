@@ -5,6 +5,8 @@
             --copy-bytes B --command "..." --out profiles/traffic_counters.json
     python -m paper_1909_09825_amd.profiling valu <counter_collection.csv> --command "..."
             --out profiles/valu_counters.json --md profiles/F.md
+    python -m paper_1909_09825_amd.profiling stalls <counter_collection.csv> --command "..."
+            --out profiles/F.md
 
 `trace` writes a per-kernel table (dispatches, mean duration, and for the
 radix-pass kernel the mean over the dispatches that move data, i.e. the ones
@@ -196,6 +198,45 @@ def valu_md(rec: dict) -> str:
     return "\n".join(lines) + "\n"
 
 
+STALL = ["SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+         "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_INSTS_VALU"]
+
+
+def stalls(csv_path, command: str) -> str:
+    """Where each kernel's waves spend their time: SQ wave-cycle counters per launch as
+    fractions of SQ_WAVE_CYCLES (all of them count in the same cycle units)."""
+    data = {c: load_counter(csv_path, c) for c in STALL}
+    lines = ["# rocprofv3 SQ wait and activity counters", "", f"Command: `{command}`", "",
+             "Per kernel (its main grid, data-moving dispatches), each counter summed over the "
+             "dispatch's rows and taken as a fraction of SQ_WAVE_CYCLES (the cycles its waves are "
+             "resident): waiting on anything (SQ_WAIT_ANY: memory or barrier dependencies), "
+             "waiting to issue (SQ_WAIT_INST_ANY), waiting to issue an LDS instruction "
+             "(SQ_WAIT_INST_LDS), issuing VALU (SQ_ACTIVE_INST_VALU) and LDS (SQ_ACTIVE_INST_LDS) "
+             "instructions; the fractions are per resident wave.", "",
+             "| kernel | grid | launches | us/launch (counter run) | wait any | wait issue "
+             "| wait LDS issue | VALU active | LDS active |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    for k, rows in sorted(data["SQ_WAVE_CYCLES"].items()):
+        b = base_name(k)
+        if b not in KERNEL_SOURCES:
+            continue
+        grid = main_grid(b, [g for _, g, _ in rows])
+        vals = [(v, d) for v, g, d in rows if g == grid]
+        vmax = max(v for v, _ in vals)
+        keep = [(v, d) for v, d in vals if v > 0.05 * vmax] or vals
+        wc = sum(v for v, _ in keep) / len(keep)
+
+        def frac(c):
+            cv = [v for v, g, _ in data[c].get(k, []) if g == grid]
+            cv = sorted(cv)[-len(keep):] if cv else [0.0]
+            return (sum(cv) / len(cv)) / wc if wc > 0 else 0.0
+        us = sum(d for _, d in keep) / len(keep)
+        lines.append(f"| `{k}` | {grid} | {len(keep)} | {us:.1f} | {frac('SQ_WAIT_ANY'):.3f} | "
+                     f"{frac('SQ_WAIT_INST_ANY'):.3f} | {frac('SQ_WAIT_INST_LDS'):.3f} | "
+                     f"{frac('SQ_ACTIVE_INST_VALU'):.3f} | {frac('SQ_ACTIVE_INST_LDS'):.3f} |")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -214,8 +255,15 @@ def main():
     v.add_argument("--command", required=True)
     v.add_argument("--out", required=True)
     v.add_argument("--md", required=True)
+    w = sub.add_parser("stalls")
+    w.add_argument("csv")
+    w.add_argument("--command", required=True)
+    w.add_argument("--out", required=True)
     a = ap.parse_args()
-    if a.cmd == "trace":
+    if a.cmd == "stalls":
+        with open(a.out, "w") as f:
+            f.write(stalls(a.csv, a.command))
+    elif a.cmd == "trace":
         with open(a.out, "w") as f:
             f.write(trace_summary(a.csv, a.command))
     elif a.cmd == "traffic":
