@@ -262,15 +262,16 @@ __global__ __launch_bounds__(256) void k_seg_scatter(const SegInfo* __restrict__
     const int64_t p = ch.start + (int64_t)wave * (kBChunk / 4) + r * kWave + lane;
     const bool valid = p < end;
     const uint32_t b = valid ? bucket_of(quant_key(z[r], sg.scale, l, qs), sg.nb_log2) : 0u;
-    uint64_t peers = __ballot(valid);
-    for (int bit = 0; bit < sg.nb_log2; ++bit) {
-      const bool on = (b >> bit) & 1u;
-      const uint64_t bal = __ballot(on);
-      peers &= on ? bal : ~bal;
+    const uint64_t live = __ballot(valid);
+    uint32_t pl = (uint32_t)live, ph = (uint32_t)(live >> 32);
+    for (int bit = 0; bit < sg.nb_log2; ++bit) {   // lanes with the same bucket, as in block_rank
+      const int32_t m = (int32_t)(b << (31 - bit)) >> 31;
+      const uint64_t bal = __ballot(m < 0);
+      pl &= ~((uint32_t)bal ^ (uint32_t)m);
+      ph &= ~((uint32_t)(bal >> 32) ^ (uint32_t)m);
     }
-    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
-    const uint32_t cnt = (uint32_t)__popcll(peers);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(ph, __builtin_amdgcn_mbcnt_lo(pl, 0u));
+    const uint32_t cnt = (uint32_t)__popc(pl) + (uint32_t)__popc(ph);
     const uint32_t before = valid ? wcnt[wave * nb + b] : 0u;
     __builtin_amdgcn_wave_barrier();
     if (valid && below == 0u) wcnt[wave * nb + b] = before + cnt;
@@ -330,16 +331,19 @@ __device__ __forceinline__ void block_rank(const uint64_t* key, const bool* vali
   for (int i = 0; i < kBSortItems; ++i) {
     const uint32_t dig = (uint32_t)(key[i] >> shift) & 0xffu;
     if (valid[i]) atomicAdd(&lds.thist[dig], 1u);
-    uint64_t peers = __ballot(valid[i]);
+    // Lanes with the same digit: per digit bit, the ballot where the lane's
+    // bit is set, else its complement (ballot XOR the bit as a sign mask).
+    const uint64_t live = __ballot(valid[i]);
+    uint32_t pl = (uint32_t)live, ph = (uint32_t)(live >> 32);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
-      const bool on = (dig >> bit) & 1u;
-      const uint64_t bal = __ballot(on);
-      peers &= on ? bal : ~bal;
+      const int32_t m = (int32_t)(dig << (31 - bit)) >> 31;
+      const uint64_t bal = __ballot(m < 0);
+      pl &= ~((uint32_t)bal ^ (uint32_t)m);
+      ph &= ~((uint32_t)(bal >> 32) ^ (uint32_t)m);
     }
-    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
-    const uint32_t cnt = (uint32_t)__popcll(peers);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(ph, __builtin_amdgcn_mbcnt_lo(pl, 0u));
+    const uint32_t cnt = (uint32_t)__popc(pl) + (uint32_t)__popc(ph);
     const uint32_t before = lds.wcnt[wave][dig];
     __builtin_amdgcn_wave_barrier();
     if (valid[i] && below == 0u) lds.wcnt[wave][dig] = before + cnt;

@@ -447,25 +447,28 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   }
 
   // Stable ranking inside the wave, items in order (i, lane): lanes with the
-  // same digit are found with 8 ballots; the lowest lane of each group
-  // advances the wave's running count.
+  // same digit are found with one ballot per digit bit (a lane keeps the
+  // ballot's lanes where its own bit is set, the others where it is clear:
+  // ballot XOR the lane's bit as a sign mask, inverted); the lowest lane of
+  // each group advances the wave's running count.
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
     const int64_t p = base + i * kWave + lane;
     const bool valid = p < P;
     const uint32_t dig = (uint32_t)(key[i] >> shift) & mask;
-    uint64_t peers = __ballot(valid);
+    const uint64_t live = __ballot(valid);
+    uint32_t pl = (uint32_t)live, ph = (uint32_t)(live >> 32);
 #pragma unroll
     for (int bit = 0; bit < kSortBits; ++bit) {
       if (bit < dbits) {   // uniform: the last bit only for 9-bit digits
-        const bool on = (dig >> bit) & 1u;
-        const uint64_t bal = __ballot(on);
-        peers &= on ? bal : ~bal;
+        const int32_t m = (int32_t)(dig << (31 - bit)) >> 31;   // the lane's bit as a sign mask
+        const uint64_t bal = __ballot(m < 0);
+        pl &= ~((uint32_t)bal ^ (uint32_t)m);
+        ph &= ~((uint32_t)(bal >> 32) ^ (uint32_t)m);
       }
     }
-    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
-    const uint32_t count = (uint32_t)__popcll(peers);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(ph, __builtin_amdgcn_mbcnt_lo(pl, 0u));
+    const uint32_t count = (uint32_t)__popc(pl) + (uint32_t)__popc(ph);
     const uint32_t before = wcnt[wave][dig];
     __builtin_amdgcn_wave_barrier();
     if (valid && below == 0u) wcnt[wave][dig] = (uint16_t)(before + count);
