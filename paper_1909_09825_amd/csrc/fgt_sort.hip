@@ -353,9 +353,12 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     uint32_t* __restrict__ tile_ctr, uint64_t* lb_cur, uint64_t* lb_next,
     uint32_t* __restrict__ status) {
   using K = typename KeyOf<T>::type;
-  __shared__ uint16_t wcnt[kSortWaves][kSortRadix];   // per-wave running digit counts, then wave offsets
-  __shared__ uint32_t tstart[kSortRadix];             // tile-local exclusive digit starts
-  __shared__ uint32_t gbase[kSortRadix];              // global output position of each digit's run
+  // Per-wave running digit counts, then each wave's first slot per digit in
+  // the tile's digit order (tile-local digit start + earlier waves' counts).
+  __shared__ uint16_t wcnt[kSortWaves][kSortRadix];
+  // Output position of a digit's run minus its tile-local start: key j of the
+  // digit-sorted tile goes to goff[digit] + j.
+  __shared__ uint32_t goff[kSortRadix];
   __shared__ uint32_t wsum[kSortRadix / kWave];
   __shared__ uint32_t thist[kSortRadix];               // tile digit histogram
   __shared__ K stage[kSortTile];                  // keys, then (reused) payloads, in digit order
@@ -477,6 +480,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   }
 
   // Exclusive scan of the tile histogram over digits (thread tid owns digit tid).
+  uint32_t tstart = 0u;   // the digit's tile-local start (digit threads)
   {
     uint32_t incl = tcount;
 #pragma unroll
@@ -489,9 +493,9 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     if (digit_thread) {
       uint32_t before = 0u;
       for (int w = 0; w < wave; ++w) before += wsum[w];
-      tstart[tid] = before + incl - tcount;
-      // running per-wave counts -> exclusive wave offsets
-      uint32_t run_sum = 0u;
+      tstart = before + incl - tcount;
+      // running per-wave counts -> each wave's first slot (at most kSortTile)
+      uint32_t run_sum = tstart;
 #pragma unroll
       for (int w = 0; w < kSortWaves; ++w) {
         const uint32_t c = wcnt[w][tid];
@@ -508,13 +512,15 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   // buffer) and write each digit's run to its global position.
   const int64_t tile_begin = (int64_t)tile * kSortTile;
   const int nvalid = (int)((P - tile_begin) < kSortTile ? (P - tile_begin) : kSortTile);
+  // All slot reads are issued before the stage writes, so their LDS round
+  // trips overlap.
   uint32_t pos[kSortItems];
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    const uint32_t dig = (uint32_t)(key[i] >> shift) & mask;
-    pos[i] = tstart[dig] + wcnt[wave][dig] + rank[i];
+  for (int i = 0; i < kSortItems; ++i)
+    pos[i] = wcnt[wave][(uint32_t)(key[i] >> shift) & mask] + rank[i];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i)
     if (base + i * kWave + lane < P && pos[i] < (uint32_t)kSortTile) stage[pos[i]] = key[i];
-  }
 
   // Decoupled look-back over earlier tiles for this digit (after the LDS sort,
   // which gives predecessors time to publish).
@@ -573,7 +579,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     }
     __hip_atomic_store(&lb_cur[(size_t)tile * kSortRadix + tid], kFlagPrefix | (excl + tcount),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    gbase[tid] = dig_off[d * kSortRadix + tid] + (uint32_t)excl;
+    goff[tid] = dig_off[d * kSortRadix + tid] + (uint32_t)excl - tstart;
   }
   __syncthreads();
   // Each thread visits the same positions j in both write loops; the output
@@ -582,18 +588,27 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   // keys) in place of the keys: the scans read them as they are.
   const bool last = d == pass->last_pass;
   const Codec<T> cd = codec_of<T>(pass);
+  // Stage keys, then their runs' offsets, then the stores: each phase issues
+  // all of its LDS reads before any result is used.
+  K ks[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int j = tid + r * kSortThreads;
+    ks[r] = j < nvalid ? stage[j] : (K)0;
+  }
+  uint32_t go[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) go[r] = goff[(uint32_t)(ks[r] >> shift) & mask];
   uint32_t outpos[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int j = tid + r * kSortThreads;
     outpos[r] = 0xffffffffu;
     if (j < nvalid) {
-      const K k = stage[j];
-      const uint32_t dig = (uint32_t)(k >> shift) & mask;
-      const uint64_t out = gbase[dig] + (uint64_t)(j - (int)tstart[dig]);
+      const uint64_t out = (uint64_t)go[r] + (uint64_t)j;
       if (out < (uint64_t)P) {
         outpos[r] = (uint32_t)out;
-        kout[out] = last ? bits_of(cd.decode(k)) : k;
+        kout[out] = last ? bits_of(cd.decode(ks[r])) : ks[r];
       }
     }
   }
