@@ -44,10 +44,55 @@ __global__ void k_clear(uint32_t* __restrict__ p, size_t n_words) {
   for (; i < n_words; i += stride) p[i] = 0u;
 }
 
-template <class T>
-__device__ __forceinline__ T load_point(const T* __restrict__ x, const T* __restrict__ y,
-                                        int64_t N, int64_t p) {
-  return p < N ? y[p] : x[p - N];
+// Visits every coordinate once, y[0..N) then x[0..P-N), grid-strided, with
+// 16-byte loads where an array is 16-byte aligned (two FP64 or four FP32
+// coordinates per load; kBatch loads issued together before any is used) and
+// single loads otherwise or for the tail.
+template <class T, int kBatch, class F>
+__device__ __forceinline__ void visit_points(const T* __restrict__ x, const T* __restrict__ y,
+                                             int64_t N, int64_t P, F f) {
+  typedef T V __attribute__((ext_vector_type(16 / sizeof(T))));
+  constexpr int L = 16 / sizeof(T);
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int part = 0; part < 2; ++part) {
+    const T* __restrict__ a = part == 0 ? y : x;
+    const int64_t n = part == 0 ? N : P - N;
+    if (n <= 0) continue;
+    int64_t done = 0;
+    if (((uintptr_t)a & 15u) == 0) {
+      const int64_t nv = n / L;
+      const V* __restrict__ av = reinterpret_cast<const V*>(a);
+      for (int64_t p0 = gtid; p0 < nv; p0 += stride * kBatch) {
+        V vb[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+          const int64_t p = p0 + i * stride;
+          vb[i] = av[p < nv ? p : p0];
+        }
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+          if (p0 + i * stride >= nv) break;
+#pragma unroll
+          for (int l = 0; l < L; ++l) f(vb[i][l]);
+        }
+      }
+      done = nv * L;
+    }
+    for (int64_t p0 = done + gtid; p0 < n; p0 += stride * kBatch) {
+      T zb[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int64_t p = p0 + i * stride;
+        zb[i] = a[p < n ? p : p0];
+      }
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        if (p0 + i * stride >= n) break;
+        f(zb[i]);
+      }
+    }
+  }
 }
 
 // Smallest and largest IEEE order key of a thread's points, and whether any
@@ -107,23 +152,7 @@ __global__ __launch_bounds__(1024) void k_range(const T* __restrict__ x, const T
                                                unsigned long long* __restrict__ range,
                                                uint32_t* __restrict__ status) {
   RangeAcc acc;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  constexpr int kBatch = 16;   // loads issued together before they are used
-  for (int part = 0; part < 2; ++part) {
-    const T* __restrict__ a = part == 0 ? y : x;
-    const int64_t n = part == 0 ? N : P - N;
-    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p0 < n;
-         p0 += stride * kBatch) {
-      T zb[kBatch];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) {
-        const int64_t p = p0 + i * stride;
-        zb[i] = p < n ? a[p] : a[p0];
-      }
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) acc.add(zb[i]);
-    }
-  }
+  visit_points<T, 8>(x, y, N, P, [&](T z) { acc.add(z); });
   acc.publish(range, status);
 }
 
@@ -234,29 +263,16 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
   const uint32_t mask = (1u << L.bits) - 1u;
 
   RangeAcc acc;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  constexpr int kBatch = 8;   // loads issued together before they are used
-  for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p0 < P; p0 += stride * kBatch) {
-    T zb[kBatch];
+  visit_points<T, 4>(x, y, N, P, [&](T z) {
+    if (kGatherRange) acc.add(z);
+    const K k = cd.encode(z);
 #pragma unroll
-    for (int i = 0; i < kBatch; ++i) {
-      const int64_t p = p0 + i * stride;
-      zb[i] = p < P ? load_point(x, y, N, p) : T(0);
+    for (int d = 0; d < D; ++d) {
+      if (d >= L.passes) continue;
+      const uint32_t dig = (uint32_t)(k >> (L.lo_bit + L.bits * d)) & mask;
+      atomicAdd(&h[d * kSortRadix + dig], 1u);
     }
-#pragma unroll
-    for (int i = 0; i < kBatch; ++i) {
-      if (p0 + i * stride >= P) break;
-      const T z = zb[i];
-      if (kGatherRange) acc.add(z);
-      const K k = cd.encode(z);
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        if (d >= L.passes) continue;
-        const uint32_t dig = (uint32_t)(k >> (L.lo_bit + L.bits * d)) & mask;
-        atomicAdd(&h[d * kSortRadix + dig], 1u);
-      }
-    }
-  }
+  });
   if (kGatherRange) acc.publish(range, status);
   __syncthreads();
   for (int i = threadIdx.x; i < D * kSortRadix; i += blockDim.x)

@@ -54,6 +54,28 @@ def test_shapes(M, N):
     full_check(pr.x, pr.y, pr.alpha, 1e-3, 6, f"shape{M}x{N}")
 
 
+@pytest.mark.parametrize("dtype,off", [(torch.float64, 1), (torch.float32, 1), (torch.float32, 2),
+                                       (torch.float32, 3)])
+def test_misaligned_inputs(dtype, off):
+    """Coordinates and strengths given as views that start off a 16-byte boundary
+    (the setup kernels then take single loads instead of 16-byte ones): results
+    bit-identical to the same values in aligned arrays."""
+    pr = W.plain(30001, 20003, 1e-4, 6, cfg=12, sub=off)
+    say(f"[gpu] misaligned views, {dtype}, offset {off} elements")
+    p = fgt.plan(1e-4, 6, dtype)
+    dev = torch.device("cuda")
+    def view(v):
+        buf = torch.zeros(len(v) + off, dtype=dtype, device=dev)
+        buf[off:] = torch.from_numpy(v).to(dev, dtype)
+        return buf[off:]
+    X, Y, A = view(pr.x), view(pr.y), view(pr.alpha)
+    assert X.data_ptr() % 16 != 0 and Y.data_ptr() % 16 != 0
+    u1 = fgt.eval(X, Y, A, p)
+    u0 = fgt.eval(X.clone(), Y.clone(), A.clone(), p)
+    assert torch.equal(u0.view(torch.int64 if dtype == torch.float64 else torch.int32),
+                       u1.view(torch.int64 if dtype == torch.float64 else torch.int32))
+
+
 def test_no_sources_gives_zero():
     say("[gpu] N = 0")
     p = fgt.plan(1e-3, 6)
