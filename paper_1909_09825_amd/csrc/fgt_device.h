@@ -65,20 +65,41 @@ template <int CTRL, int ROWS>
 __device__ __forceinline__ float dpp_move(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
 }
+// Row shift: lanes shifted in from outside the row read 0 (bound_ctrl), so
+// no zero source register is needed.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
 template <class T>
 __device__ __forceinline__ T wave_inclusive_sum(T v) {
-  v += dpp_move<0x111, 0xf>(v);   // row_shr:1
-  v += dpp_move<0x112, 0xf>(v);   // row_shr:2
-  v += dpp_move<0x114, 0xf>(v);   // row_shr:4
-  v += dpp_move<0x118, 0xf>(v);   // row_shr:8
+  v += dpp_shift<0x111>(v);       // row_shr:1
+  v += dpp_shift<0x112>(v);       // row_shr:2
+  v += dpp_shift<0x114>(v);       // row_shr:4
+  v += dpp_shift<0x118>(v);       // row_shr:8
   v += dpp_move<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
   v += dpp_move<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
   return v;
 }
+// Lane l's value, in every lane (a scalar read).
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
 // The sum over the whole wave, in every lane.
 template <class T>
 __device__ __forceinline__ T wave_total(T v) {
-  return __shfl(wave_inclusive_sum(v), kWave - 1, kWave);
+  return lane_value(wave_inclusive_sum(v), kWave - 1);
 }
 
 template <class T> struct Prec;

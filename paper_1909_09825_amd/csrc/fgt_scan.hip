@@ -439,11 +439,10 @@ __device__ __forceinline__ void final_fast_body(const Modes& md, const T* dz, co
         pw[j] *= sc[j];
       }
       const T inc = wave_inclusive_sum(nu);
-      const T tot = __shfl(inc, kWave - 1, kWave);
-      const T exc = shfl_up(inc, 1);
+      const T tot = lane_value(inc, kWave - 1);
       const T f = T(kInvFact.v[m]);
-      pre[m] = (lane > 0 ? exc : T(0)) * f;
-      suf[m] = (tot - inc) * f;
+      pre[m] = (inc - nu) * f;   // the lanes before this one
+      suf[m] = (tot - inc) * f;  // the lanes after it
     }
   }
   const T xf = g.zs - g.c;
