@@ -320,7 +320,6 @@ __device__ __forceinline__ void block_rank(const uint64_t* key, const bool* vali
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   constexpr int W = kBSortThreads / kWave;
   for (int i = tid; i < W * kRadix; i += kBSortThreads) (&lds.wcnt[0][0])[i] = 0u;
-  if (tid < kRadix) lds.thist[tid] = 0u;
   __syncthreads();
   uint32_t rank[kBSortItems];
 #pragma unroll
@@ -330,7 +329,6 @@ __device__ __forceinline__ void block_rank(const uint64_t* key, const bool* vali
 #pragma unroll
   for (int i = 0; i < kBSortItems; ++i) {
     const uint32_t dig = (uint32_t)(key[i] >> shift) & 0xffu;
-    if (valid[i]) atomicAdd(&lds.thist[dig], 1u);
     // Lanes with the same digit: per digit bit, the ballot where the lane's
     // bit is set, else its complement (ballot XOR the bit as a sign mask).
     const uint64_t live = __ballot(valid[i]);
@@ -353,19 +351,21 @@ __device__ __forceinline__ void block_rank(const uint64_t* key, const bool* vali
   }
   __syncthreads();
   if (tid < kRadix) {
-    const uint32_t c = lds.thist[tid];
+    // The tile's count of digit tid is the sum of the waves' counts; they
+    // become exclusive wave offsets.
+    uint32_t c = 0u;
+    for (int w = 0; w < W; ++w) {
+      const uint32_t v = lds.wcnt[w][tid];
+      lds.wcnt[w][tid] = c;
+      c += v;
+    }
+    lds.thist[tid] = c;
     uint32_t inc = c;
     for (int o = 1; o < kWave; o <<= 1) {
       const uint32_t v = __shfl_up(inc, (unsigned)o, kWave);
       if (lane >= o) inc += v;
     }
     if (lane == kWave - 1) lds.wsum[wave] = inc;
-    uint32_t run = 0u;
-    for (int w = 0; w < W; ++w) {
-      const uint32_t v = lds.wcnt[w][tid];
-      lds.wcnt[w][tid] = run;
-      run += v;
-    }
     lds.tstart[tid] = inc - c;   // completed below with the earlier waves' sums
   }
   __syncthreads();
