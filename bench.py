@@ -52,6 +52,7 @@ VALU_SLOTS_PER_S = 256 * 4 * 2.4e9 / 4
 METRIC = "(M+N)·modes/s and transforms/s at 6 digits, fwd vs fwd+bwd, % HBM roofline"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_counters.json")
+MIX_FILE = os.path.join(ROOT, "profiles", "valu_mix_counters.json")
 
 
 def parse():
@@ -104,6 +105,16 @@ def valu_frac(kernel: str, ms_launch: float):
     if not rec or ms_launch <= 0:
         return None
     return round(float(rec["valu_insts_per_launch"]) / (ms_launch * 1e-3 * VALU_SLOTS_PER_S), 4)
+
+
+def fp64_frac(kernel: str, ms_launch: float):
+    """FP64 operations per launch from the committed instruction-mix counters (an FMA
+    counted as two) over the launch's measured time, as a fraction of the FP64 vector peak."""
+    rec = _counter_record(MIX_FILE, kernel)
+    if not rec or ms_launch <= 0:
+        return None
+    return round(float(rec["fp64_ops_per_launch"]) / (ms_launch * 1e-3)
+                 / (FP64_VALU_PEAK_TFLOPS * 1e12), 4)
 
 
 def timed(fn, steps, warmup, torch):
@@ -524,7 +535,8 @@ def main():
         kernels[k] = {"ms_per_launch": round(ms, 5), "launches_per_step": launches[k],
                       "alg_bytes_per_launch": int(alg[k]), "GBps": round(g, 1),
                       "hbm_frac": round(g / HBM_PEAK_GBS, 4),
-                      "valu_frac": valu_frac(counter_name[k], ms) if not args.fp32 else None}
+                      "valu_frac": valu_frac(counter_name[k], ms) if not args.fp32 else None,
+                      "fp64_frac": fp64_frac(counter_name[k], ms) if not args.fp32 else None}
     out = {
         "metric": METRIC,
         "value": P * n_modes / (ms_step * 1e-3),

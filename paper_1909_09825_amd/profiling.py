@@ -7,6 +7,8 @@
             --out profiles/valu_counters.json --md profiles/F.md
     python -m paper_1909_09825_amd.profiling stalls <counter_collection.csv> --command "..."
             --out profiles/F.md
+    python -m paper_1909_09825_amd.profiling mix <counter_collection.csv> --command "..."
+            --out profiles/F.md --json profiles/valu_mix_counters.json
 
 `trace` writes a per-kernel table (dispatches, mean duration, and for the
 radix-pass kernel the mean over the dispatches that move data, i.e. the ones
@@ -237,6 +239,65 @@ def stalls(csv_path, command: str) -> str:
     return "\n".join(lines) + "\n"
 
 
+MIX = ["SQ_INSTS_VALU", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+       "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_VALU_INT32",
+       "SQ_INSTS_VALU_INT64"]
+FP64_PEAK_FLOPS = 78.6e12   # MI355X FP64 vector, an FMA counted as two operations
+
+
+def mix(csv_path, command: str):
+    """FP64 operation rate and instruction mix per kernel (wave instructions x 64 lanes):
+    the markdown table and a record per kernel (FP64 operations per launch, sources hash)."""
+    data = {c: load_counter(csv_path, c) for c in MIX}
+    rec = {"_about": ("FP64 operations per launch (64 lanes x (add + mul + 2 fma) wave "
+                      "instructions) from SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 on each kernel's main grid"),
+           "command": command}
+    lines = ["# rocprofv3 VALU instruction mix and FP64 rate", "", f"Command: `{command}`", "",
+             "Per kernel (its main grid, data-moving dispatches): wave-level VALU instructions per "
+             "launch, the FP64 add, multiply and FMA instructions among them, transcendental and "
+             "integer instructions; FP64 FLOP/s = 64 lanes x (add + mul + 2 fma) over the counter "
+             "run's own dispatch time, against the 78.6 TFLOP/s FP64 vector peak; f64 share = "
+             "FP64 arithmetic instructions / all VALU instructions.", "",
+             "| kernel | grid | us/launch (counter run) | VALU insts | FP64 add | FP64 mul | FP64 fma "
+             "| trans F64 | trans F32 | int32 | int64 | FP64 TFLOP/s | of peak | f64 share |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for k, rows in sorted(data["SQ_INSTS_VALU"].items()):
+        b = base_name(k)
+        if b not in KERNEL_SOURCES:
+            continue
+        grid = main_grid(b, [g for _, g, _ in rows])
+        vals = [(v, d) for v, g, d in rows if g == grid]
+        vmax = max(v for v, _ in vals)
+        keep = [(v, d) for v, d in vals if v > 0.05 * vmax] or vals
+        valu = sum(v for v, _ in keep) / len(keep)
+        us = sum(d for _, d in keep) / len(keep)
+
+        def per(c):
+            cv = [v for v, g, _ in data[c].get(k, []) if g == grid]
+            cv = sorted(cv)[-len(keep):] if cv else [0.0]
+            return sum(cv) / len(cv)
+        add, mul, fma = per("SQ_INSTS_VALU_ADD_F64"), per("SQ_INSTS_VALU_MUL_F64"), \
+            per("SQ_INSTS_VALU_FMA_F64")
+        flops = 64.0 * (add + mul + 2.0 * fma) / (us * 1e-6) if us > 0 else 0.0
+        # The base name stands for the instantiation with the most VALU work (the
+        # common one); the others keep their full names.
+        r = {"kernel": k, "grid": grid, "fp64_ops_per_launch": 64.0 * (add + mul + 2.0 * fma),
+             "valu_insts_per_launch": valu, "us_per_launch_pmc": us,
+             "sources": KERNEL_SOURCES[b], "source_sha": source_hash(KERNEL_SOURCES[b])}
+        if b not in rec or rec[b]["valu_insts_per_launch"] < valu:
+            if b in rec:
+                rec[rec[b]["kernel"]] = rec[b]
+            rec[b] = r
+        else:
+            rec[k] = r
+        lines.append(f"| `{k}` | {grid} | {us:.1f} | {valu:.4g} | {add:.3g} | {mul:.3g} | {fma:.3g} | "
+                     f"{per('SQ_INSTS_VALU_TRANS_F64'):.3g} | {per('SQ_INSTS_VALU_TRANS_F32'):.3g} | "
+                     f"{per('SQ_INSTS_VALU_INT32'):.3g} | {per('SQ_INSTS_VALU_INT64'):.3g} | "
+                     f"{flops / 1e12:.2f} | {flops / FP64_PEAK_FLOPS:.3f} | "
+                     f"{(add + mul + fma) / valu if valu else 0.0:.2f} |")
+    return "\n".join(lines) + "\n", rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -255,12 +316,24 @@ def main():
     v.add_argument("--command", required=True)
     v.add_argument("--out", required=True)
     v.add_argument("--md", required=True)
+    x = sub.add_parser("mix")
+    x.add_argument("csv")
+    x.add_argument("--command", required=True)
+    x.add_argument("--out", required=True)
+    x.add_argument("--json", required=True)
     w = sub.add_parser("stalls")
     w.add_argument("csv")
     w.add_argument("--command", required=True)
     w.add_argument("--out", required=True)
     a = ap.parse_args()
-    if a.cmd == "stalls":
+    if a.cmd == "mix":
+        text, rec = mix(a.csv, a.command)
+        with open(a.out, "w") as f:
+            f.write(text)
+        with open(a.json, "w") as f:
+            json.dump(rec, f, indent=1)
+            f.write("\n")
+    elif a.cmd == "stalls":
         with open(a.out, "w") as f:
             f.write(stalls(a.csv, a.command))
     elif a.cmd == "trace":
