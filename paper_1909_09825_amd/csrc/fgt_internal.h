@@ -232,7 +232,7 @@ struct PassInfo {
   int32_t run[8];     // 1 if radix pass d moves data
   int32_t src[8];     // 0/1: key buffer it reads, 2: the raw coordinates
   int32_t final_buf;  // buffer that holds the sorted coordinates at the end
-  int32_t last_pass;  // the last pass that runs; it also writes coordinates, strengths and ids
+  int32_t last_pass;  // the last pass that runs; it also writes the coordinates and ids
   int32_t skipped_low;  // low key bits left unsorted (below the plan's key resolution)
   int32_t shift[8];     // lowest bit of pass d's digit
   int32_t bits;         // digit width of this sort, 8 or 9
