@@ -17,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfgt.so")
-SOURCES = ["fgt_api.hip", "fgt_sort.hip", "fgt_scan.hip", "fgt_batch.hip", "fgt_adjoint.hip"]
+SOURCES = ["fgt_api.hip", "fgt_sort.hip", "fgt_scan.hip", "fgt_batch.hip", "fgt_adjoint.hip",
+           "fgt_small.hip"]
 ARCH = os.environ.get("FGT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

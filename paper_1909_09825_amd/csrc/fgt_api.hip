@@ -217,12 +217,33 @@ struct fgt_plan_s {
 namespace fgt {
 namespace {
 
-// Sort (when `sort` is set) and evaluate u at the targets.
+}  // namespace
+
+// fgt_eval of a small problem in one launch (fgt_small.hip); *done is false,
+// and nothing enqueued, when the problem is too large for it.
+template <class T>
+hipError_t small_eval(const Workspace& w, const Modes& md, const T* x, int64_t M, const T* y,
+                      const T* alpha, int64_t N, T* u, hipStream_t s, bool* done);
+
+namespace {
+
+// Sort (when `sort` is set) and evaluate u at the targets.  Small problems run
+// in one workgroup (the multi-kernel path is launch-latency bound there).
 template <class T>
 hipError_t forward(const fgt_plan_s* plan, const Workspace& w, const void* x, int64_t M,
                    const void* y, const void* alpha, int64_t N, void* u, bool sort,
                    hipStream_t s, Timeline* tl) {
   const int64_t P = M + N;
+  if (sort) {
+    bool done = false;
+    tl->mark(s);
+    const hipError_t e = small_eval<T>(w, plan->modes, (const T*)x, M, (const T*)y,
+                                       (const T*)alpha, N, (T*)u, s, &done);
+    if (done || e != hipSuccess) {
+      tl->mark(s);
+      return e;
+    }
+  }
   if (sort) {
     const hipError_t e =
         sort_points<T>(w, (const T*)x, M, (const T*)y, N, plan->modes.sort, s, tl);
