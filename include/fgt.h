@@ -107,7 +107,11 @@ size_t fgt_workspace_size(fgt_plan_t plan, int64_t M, int64_t N);
  *                are clobbered.  One workspace may not be used by two calls at
  *                once.
  *   u            may not alias x, y, alpha or ws.
- * M == 0 enqueues nothing; N == 0 writes zeros.
+ * M == 0 enqueues nothing; N == 0 writes zeros.  Problems with M + N <= 4096
+ * run as one workgroup in one launch (the sort then orders every key bit);
+ * larger ones as the sequence of sort and scan kernels.  Either way the
+ * workspace afterwards holds the sorted state fgt_eval_sorted and fgt_backward
+ * (FGT_SORTED) start from.
  * Non-finite coordinates are detected on the device and reported by
  * fgt_last_device_status; u is then unspecified.
  * Errors: FGT_EINVAL (negative sizes, M + N >= 2^32, null pointer with a
@@ -165,7 +169,9 @@ int fgt_eval_self(fgt_plan_t plan, const void* x, int64_t N, const void* alpha, 
 #define FGT_SORT_EXACT 4
 
 /*
- * fgt_sort -- the sort step of Section 4 alone, exactly as fgt_eval runs it:
+ * fgt_sort -- the sort step of Section 4 alone, exactly as fgt_eval runs it
+ * for M + N > 4096 (fgt_eval sorts smaller problems with every key bit, as
+ * FGT_SORT_EXACT does here):
  * the merged points [y_1..y_N, x_1..x_M] in ascending order (the paper sorts
  * sources and targets before the recurrences and times that step on its
  * own, Section 5).  Writes, per sorted position p, the merged index perm[p]
