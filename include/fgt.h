@@ -363,6 +363,8 @@ int fgt_last_device_status(void* ws, hipStream_t stream);
  * group (phase names: fgt_profile_phase_name).  fgt_profile_end waits for the
  * recorded events and returns, per phase, the milliseconds summed over the
  * calls (ms[max_phases], host memory), the number of phases and of calls.
+ * A number of phases above the number of phase names means that some call
+ * marked more phase boundaries than the profiler records (a library defect).
  * Not thread-safe; meant for single-threaded benchmark drivers.
  */
 int fgt_profile_begin(void);

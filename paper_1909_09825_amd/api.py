@@ -531,6 +531,8 @@ def profile_end() -> tuple[dict, int]:
     out = {}
     for i in range(n_ph.value):
         name = lib.fgt_profile_phase_name(i).decode()
+        if not name:
+            raise RuntimeError("fgt_profile_end: a call marked more phases than the profiler records")
         if ms[i] > 0:
             out[name] = ms[i]
     return out, n_calls.value

@@ -215,15 +215,13 @@ struct fgt_plan_s {
 };
 
 namespace fgt {
-namespace {
 
-}  // namespace
-
-// fgt_eval of a small problem in one launch (fgt_small.hip); *done is false,
-// and nothing enqueued, when the problem is too large for it.
+// fgt_eval of a small problem in one launch (fgt_small.hip), recorded as one
+// phase on tl; *done is false, and nothing enqueued or recorded, when the
+// problem is too large for it.
 template <class T>
 hipError_t small_eval(const Workspace& w, const Modes& md, const T* x, int64_t M, const T* y,
-                      const T* alpha, int64_t N, T* u, hipStream_t s, bool* done);
+                      const T* alpha, int64_t N, T* u, hipStream_t s, Timeline* tl, bool* done);
 
 namespace {
 
@@ -236,13 +234,9 @@ hipError_t forward(const fgt_plan_s* plan, const Workspace& w, const void* x, in
   const int64_t P = M + N;
   if (sort) {
     bool done = false;
-    tl->mark(s);
     const hipError_t e = small_eval<T>(w, plan->modes, (const T*)x, M, (const T*)y,
-                                       (const T*)alpha, N, (T*)u, s, &done);
-    if (done || e != hipSuccess) {
-      tl->mark(s);
-      return e;
-    }
+                                       (const T*)alpha, N, (T*)u, s, tl, &done);
+    if (done || e != hipSuccess) return e;
   }
   if (sort) {
     const hipError_t e =
@@ -964,7 +958,10 @@ int fgt_profile_end(double* ms, int max_phases, int* n_phases, int* n_calls) {
   for (auto& c : fgt::g_prof.calls) {
     // FP32 has 4 radix passes: map its phases onto the FP64 names.
     const int passes = c.f64 ? 8 : 4;
-    for (int i = 0; i + 1 < c.n; ++i) {
+    // More marks than events: reported as more phases than there are names.
+    if (c.n > fgt::kMaxPhases + 1 && c.n - 1 > phases) phases = c.n - 1;
+    const int recorded = c.n < fgt::kMaxPhases + 1 ? c.n : fgt::kMaxPhases + 1;
+    for (int i = 0; i + 1 < recorded; ++i) {
       float t = 0.f;
       if (hipEventSynchronize(c.ev[i + 1]) != hipSuccess ||
           hipEventElapsedTime(&t, c.ev[i], c.ev[i + 1]) != hipSuccess) {
@@ -972,6 +969,7 @@ int fgt_profile_end(double* ms, int max_phases, int* n_phases, int* n_calls) {
         continue;
       }
       const int name = i <= passes ? i : i + (8 - passes);
+      if (name >= fgt::kMaxPhases) continue;
       acc[name] += t;
       if (name + 1 > phases) phases = name + 1;
     }

@@ -308,9 +308,11 @@ struct Workspace {
 constexpr int kMaxPhases = 12;   // setup, 8 radix passes, tile reduce, carry, tile final
 struct Timeline {
   hipEvent_t* ev = nullptr;
-  int n = 0, cap = 0;
+  int n = 0, cap = 0;   // n: marks made (recorded while n < cap)
   void mark(hipStream_t s) {
-    if (ev && n < cap) (void)hipEventRecord(ev[n++], s);
+    if (!ev) return;
+    if (n < cap) (void)hipEventRecord(ev[n], s);
+    ++n;
   }
 };
 

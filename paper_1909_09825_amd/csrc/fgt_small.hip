@@ -211,39 +211,41 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(
 
 template <class T, int NM>
 hipError_t small_nm(const Workspace& w, const Modes& md, const T* x, int64_t M, const T* y,
-                    const T* alpha, int64_t N, T* u, hipStream_t s) {
+                    const T* alpha, int64_t N, T* u, hipStream_t s, Timeline* tl) {
+  tl->mark(s);
   hipLaunchKernelGGL((k_small<T, NM>), dim3(1), dim3(kSmallThreads), 0, s, x, M, y, alpha, N, md,
                      u, (T*)w.keys[0], w.ids, (T*)w.b, w.pass, w.status);
+  tl->mark(s);
   return hipGetLastError();
 }
 
 }  // namespace
 
-// fgt_eval for P = M + N <= kSmallMax in one launch; *done is false (and
-// nothing is enqueued) for larger problems.
+// fgt_eval for P = M + N <= kSmallMax in one launch, one phase on tl; *done
+// is false (and nothing is enqueued or recorded) for larger problems.
 template <class T>
 hipError_t small_eval(const Workspace& w, const Modes& md, const T* x, int64_t M, const T* y,
-                      const T* alpha, int64_t N, T* u, hipStream_t s, bool* done) {
+                      const T* alpha, int64_t N, T* u, hipStream_t s, Timeline* tl, bool* done) {
   *done = false;
   if (M + N > kSmallMax || M <= 0 || N <= 0) return hipSuccess;
   *done = true;
   switch (md.n) {
-    case 1: return small_nm<T, 1>(w, md, x, M, y, alpha, N, u, s);
-    case 2: return small_nm<T, 2>(w, md, x, M, y, alpha, N, u, s);
-    case 3: return small_nm<T, 3>(w, md, x, M, y, alpha, N, u, s);
-    case 4: return small_nm<T, 4>(w, md, x, M, y, alpha, N, u, s);
-    case 5: return small_nm<T, 5>(w, md, x, M, y, alpha, N, u, s);
-    case 6: return small_nm<T, 6>(w, md, x, M, y, alpha, N, u, s);
-    case 7: return small_nm<T, 7>(w, md, x, M, y, alpha, N, u, s);
+    case 1: return small_nm<T, 1>(w, md, x, M, y, alpha, N, u, s, tl);
+    case 2: return small_nm<T, 2>(w, md, x, M, y, alpha, N, u, s, tl);
+    case 3: return small_nm<T, 3>(w, md, x, M, y, alpha, N, u, s, tl);
+    case 4: return small_nm<T, 4>(w, md, x, M, y, alpha, N, u, s, tl);
+    case 5: return small_nm<T, 5>(w, md, x, M, y, alpha, N, u, s, tl);
+    case 6: return small_nm<T, 6>(w, md, x, M, y, alpha, N, u, s, tl);
+    case 7: return small_nm<T, 7>(w, md, x, M, y, alpha, N, u, s, tl);
     default: *done = false; return hipErrorInvalidValue;
   }
 }
 
 template hipError_t small_eval<double>(const Workspace&, const Modes&, const double*, int64_t,
                                        const double*, const double*, int64_t, double*,
-                                       hipStream_t, bool*);
+                                       hipStream_t, Timeline*, bool*);
 template hipError_t small_eval<float>(const Workspace&, const Modes&, const float*, int64_t,
                                       const float*, const float*, int64_t, float*, hipStream_t,
-                                      bool*);
+                                      Timeline*, bool*);
 
 }  // namespace fgt
