@@ -152,7 +152,29 @@ __global__ __launch_bounds__(1024) void k_range(const T* __restrict__ x, const T
                                                unsigned long long* __restrict__ range,
                                                uint32_t* __restrict__ status) {
   RangeAcc acc;
-  visit_points<T, 8>(x, y, N, P, [&](T z) { acc.add(z); });
+  if constexpr (sizeof(T) == 8) {
+    // Folded as doubles (one min and one max instruction a point; -0 and +0
+    // map to the same key) and converted to order keys once.  Any non-finite
+    // point publishes the range [-inf, +inf]: like a NaN's key it selects IEEE
+    // keys with every bit sorted.
+    double lo = INFINITY, hi = -INFINITY;
+    uint32_t gran = 0u;
+    bool bad = false;
+    visit_points<T, 8>(x, y, N, P, [&](T z) {
+      lo = fmin(lo, z);
+      hi = fmax(hi, z);
+      const bool fin = isfinite(z);
+      bad |= !fin;
+      const uint32_t gv = (z != 0.0 && fin) ? (uint32_t)(2048 - granularity_exp(z)) : 0u;
+      gran = gv > gran ? gv : gran;
+    });
+    acc.kmin = bad ? to_key(-INFINITY) : to_key(lo);
+    acc.kmax = bad ? to_key(INFINITY) : to_key(hi);
+    acc.gran = gran;
+    acc.bad = bad;
+  } else {
+    visit_points<T, 8>(x, y, N, P, [&](T z) { acc.add(z); });
+  }
   acc.publish(range, status);
 }
 
@@ -263,7 +285,7 @@ __global__ __launch_bounds__(256) void k_histogram(const T* __restrict__ x, cons
   const uint32_t mask = (1u << L.bits) - 1u;
 
   RangeAcc acc;
-  visit_points<T, 4>(x, y, N, P, [&](T z) {
+  visit_points<T, 8>(x, y, N, P, [&](T z) {
     if (kGatherRange) acc.add(z);
     const K k = cd.encode(z);
 #pragma unroll
@@ -360,47 +382,39 @@ __global__ __launch_bounds__(512) void k_plan(const uint32_t* __restrict__ hist,
   }
 }
 
+// LDS of one radix tile.
 template <class T>
-__global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
-    int d, const T* __restrict__ x, const T* __restrict__ y, int64_t N,
-    int64_t P, void* keys0, void* keys1, uint32_t* idx0, uint32_t* idx1,
-    uint32_t* __restrict__ ids_out,
-    const uint32_t* __restrict__ dig_off, const PassInfo* __restrict__ pass,
-    uint32_t* __restrict__ tile_ctr, uint64_t* lb_cur, uint64_t* lb_next,
-    uint32_t* __restrict__ status) {
-  using K = typename KeyOf<T>::type;
+struct SweepLds {
   // Per-wave running digit counts, then each wave's first slot per digit in
   // the tile's digit order (tile-local digit start + earlier waves' counts).
-  __shared__ uint16_t wcnt[kSortWaves][kSortRadix];
+  uint16_t wcnt[kSortWaves][kSortRadix];
   // Output position of a digit's run minus its tile-local start: key j of the
   // digit-sorted tile goes to goff[digit] + j.
-  __shared__ uint32_t goff[kSortRadix];
-  __shared__ uint32_t wsum[kSortRadix / kWave];
-  __shared__ uint32_t thist[kSortRadix];               // tile digit histogram
-  __shared__ K stage[kSortTile];                  // keys, then (reused) payloads, in digit order
-  __shared__ int s_tile;
+  uint32_t goff[kSortRadix];
+  uint32_t wsum[kSortRadix / kWave];
+  uint32_t thist[kSortRadix];                     // tile digit histogram
+  typename KeyOf<T>::type stage[kSortTile];       // keys, then (reused) payloads, in digit order
+};
 
+// One tile of a radix pass.  kFull: the tile holds kSortTile points (every
+// tile but the last), so no item needs a bounds check.
+template <class T, bool kFull>
+__device__ __forceinline__ void sweep_tile(
+    SweepLds<T>& lds, int tile, int d, const T* __restrict__ x, const T* __restrict__ y,
+    int64_t N, int64_t P, void* keys0, void* keys1, uint32_t* idx0, uint32_t* idx1,
+    uint32_t* __restrict__ ids_out, const uint32_t* __restrict__ dig_off,
+    const PassInfo* __restrict__ pass, uint64_t* lb_cur, uint32_t* __restrict__ status) {
+  using K = typename KeyOf<T>::type;
+  auto& wcnt = lds.wcnt;
+  auto& goff = lds.goff;
+  auto& wsum = lds.wsum;
+  auto& thist = lds.thist;
+  auto& stage = lds.stage;
   const int tid = threadIdx.x;
-  const int run = pass->run[d];
   const int src = pass->src[d];
   const int dbits = pass->bits;          // 8 or 9 for the whole sort
   const int ndig = 1 << dbits;
-  if (!run) {
-    // Nothing moves; still clear the other look-back buffer for the next pass
-    // that runs (none after the last: the next sort's first pass starts from
-    // the buffer k_clear zeroes, and each pass clears the one after it).
-    if (d < pass->last_pass && tid < ndig)
-      for (int64_t t = blockIdx.x; t * kSortTile < P; t += gridDim.x)
-        lb_next[(size_t)t * kSortRadix + tid] = 0ull;
-    return;
-  }
-  if (tid == 0) s_tile = (int)atomicAdd(&tile_ctr[d], 1u);
-  for (int i = tid; i < kSortWaves * kSortRadix; i += kSortThreads) (&wcnt[0][0])[i] = 0;
-  if (tid < kSortRadix) thist[tid] = 0u;
-  __syncthreads();
-  const int tile = s_tile;
   const bool digit_thread = tid < ndig;   // threads 0..ndig-1 own one digit value each
-  if (digit_thread) lb_next[(size_t)tile * kSortRadix + tid] = 0ull;
 
   const K* kin = src == 1 ? (const K*)keys1 : (const K*)keys0;
   const uint32_t* iin = src == 1 ? idx1 : idx0;
@@ -427,28 +441,32 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
       const int64_t p = base + i * kWave + lane;
-      z[i] = p >= P ? T(0)
-           : p < N  ? __builtin_nontemporal_load(&y[p])
-                    : __builtin_nontemporal_load(&x[p - N]);
-      id[i] = p < P ? (uint32_t)p : 0u;
+      z[i] = (!kFull && p >= P) ? T(0)
+           : p < N               ? __builtin_nontemporal_load(&y[p])
+                                 : __builtin_nontemporal_load(&x[p - N]);
+      id[i] = (kFull || p < P) ? (uint32_t)p : 0u;
     }
     const Codec<T> cd = codec_of<T>(pass);
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i)
-      key[i] = base + i * kWave + lane < P ? cd.encode(z[i]) : (K)0;
+      key[i] = (kFull || base + i * kWave + lane < P) ? cd.encode(z[i]) : (K)0;
   } else if (d == pass->last_pass) {
+    // The empty asm keeps the compiler from merging this loop with the one
+    // below, which would drop the nontemporal hint of the middle passes.
+    asm volatile("" ::: "memory");
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
       const int64_t p = base + i * kWave + lane;
-      key[i] = p < P ? kin[p] : (K)0;
-      id[i] = p < P ? iin[p] : 0u;
+      key[i] = (kFull || p < P) ? kin[p] : (K)0;
+      id[i] = (kFull || p < P) ? iin[p] : 0u;
     }
+    asm volatile("" ::: "memory");
   } else {
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
       const int64_t p = base + i * kWave + lane;
-      key[i] = p < P ? __builtin_nontemporal_load(&kin[p]) : (K)0;
-      id[i] = p < P ? __builtin_nontemporal_load(&iin[p]) : 0u;
+      key[i] = (kFull || p < P) ? __builtin_nontemporal_load(&kin[p]) : (K)0;
+      id[i] = (kFull || p < P) ? __builtin_nontemporal_load(&iin[p]) : 0u;
     }
   }
 
@@ -456,7 +474,8 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   // (longer) stable ranking and successors waiting on them move on sooner.
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i)
-    if (base + i * kWave + lane < P) atomicAdd(&thist[(uint32_t)(key[i] >> shift) & mask], 1u);
+    if (kFull || base + i * kWave + lane < P)
+      atomicAdd(&thist[(uint32_t)(key[i] >> shift) & mask], 1u);
   __syncthreads();
   uint32_t tcount = 0u;
   if (digit_thread) {
@@ -473,9 +492,9 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
     const int64_t p = base + i * kWave + lane;
-    const bool valid = p < P;
+    const bool valid = kFull || p < P;
     const uint32_t dig = (uint32_t)(key[i] >> shift) & mask;
-    const uint64_t live = __ballot(valid);
+    const uint64_t live = kFull ? ~0ull : __ballot(valid);
     uint32_t pl = (uint32_t)live, ph = (uint32_t)(live >> 32);
 #pragma unroll
     for (int bit = 0; bit < kSortBits; ++bit) {
@@ -527,7 +546,8 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   // Sort the tile by digit in LDS (keys first, then payloads through the same
   // buffer) and write each digit's run to its global position.
   const int64_t tile_begin = (int64_t)tile * kSortTile;
-  const int nvalid = (int)((P - tile_begin) < kSortTile ? (P - tile_begin) : kSortTile);
+  const int nvalid =
+      kFull ? kSortTile : (int)((P - tile_begin) < kSortTile ? (P - tile_begin) : kSortTile);
   // All slot reads are issued before the stage writes, so their LDS round
   // trips overlap.
   uint32_t pos[kSortItems];
@@ -536,7 +556,8 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     pos[i] = wcnt[wave][(uint32_t)(key[i] >> shift) & mask] + rank[i];
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i)
-    if (base + i * kWave + lane < P && pos[i] < (uint32_t)kSortTile) stage[pos[i]] = key[i];
+    if ((kFull || base + i * kWave + lane < P) && pos[i] < (uint32_t)kSortTile)
+      stage[pos[i]] = key[i];
 
   // Decoupled look-back over earlier tiles for this digit (after the LDS sort,
   // which gives predecessors time to publish).
@@ -610,7 +631,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int j = tid + r * kSortThreads;
-    ks[r] = j < nvalid ? stage[j] : (K)0;
+    ks[r] = (kFull || j < nvalid) ? stage[j] : (K)0;
   }
   uint32_t go[kSortItems];
 #pragma unroll
@@ -620,7 +641,7 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   for (int r = 0; r < kSortItems; ++r) {
     const int j = tid + r * kSortThreads;
     outpos[r] = 0xffffffffu;
-    if (j < nvalid) {
+    if (kFull || j < nvalid) {
       const uint64_t out = (uint64_t)go[r] + (uint64_t)j;
       if (out < (uint64_t)P) {
         outpos[r] = (uint32_t)out;
@@ -632,14 +653,14 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
   uint32_t* sid = (uint32_t*)stage;
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i)
-    if (base + i * kWave + lane < P && pos[i] < (uint32_t)kSortTile) sid[pos[i]] = id[i];
+    if ((kFull || base + i * kWave + lane < P) && pos[i] < (uint32_t)kSortTile) sid[pos[i]] = id[i];
   __syncthreads();
   // The last pass writes the final permutation to its own array, which the
   // scans keep using.
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int j = tid + r * kSortThreads;
-    if (j >= nvalid || outpos[r] == 0xffffffffu) continue;
+    if ((!kFull && j >= nvalid) || outpos[r] == 0xffffffffu) continue;
     const uint32_t out = outpos[r];
     const uint32_t id = sid[j];
     if (last)
@@ -647,6 +668,54 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     else
       iout[out] = id;
   }
+}
+
+// The last, partial tile: a call of its own, so that its bounds checks do not
+// raise the register pressure of the full tiles' code.
+template <class T>
+__device__ __noinline__ void sweep_last(
+    SweepLds<T>& lds, int tile, int d, const T* __restrict__ x, const T* __restrict__ y,
+    int64_t N, int64_t P, void* keys0, void* keys1, uint32_t* idx0, uint32_t* idx1,
+    uint32_t* __restrict__ ids_out, const uint32_t* __restrict__ dig_off,
+    const PassInfo* __restrict__ pass, uint64_t* lb_cur, uint32_t* __restrict__ status) {
+  sweep_tile<T, false>(lds, tile, d, x, y, N, P, keys0, keys1, idx0, idx1, ids_out, dig_off, pass,
+                       lb_cur, status);
+}
+
+template <class T>
+__global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
+    int d, const T* __restrict__ x, const T* __restrict__ y, int64_t N,
+    int64_t P, void* keys0, void* keys1, uint32_t* idx0, uint32_t* idx1,
+    uint32_t* __restrict__ ids_out,
+    const uint32_t* __restrict__ dig_off, const PassInfo* __restrict__ pass,
+    uint32_t* __restrict__ tile_ctr, uint64_t* lb_cur, uint64_t* lb_next,
+    uint32_t* __restrict__ status) {
+  __shared__ SweepLds<T> lds;
+  __shared__ int s_tile;
+  const int tid = threadIdx.x;
+  const int run = pass->run[d];
+  const int ndig = 1 << pass->bits;
+  if (!run) {
+    // Nothing moves; still clear the other look-back buffer for the next pass
+    // that runs (none after the last: the next sort's first pass starts from
+    // the buffer k_clear zeroes, and each pass clears the one after it).
+    if (d < pass->last_pass && tid < ndig)
+      for (int64_t t = blockIdx.x; t * kSortTile < P; t += gridDim.x)
+        lb_next[(size_t)t * kSortRadix + tid] = 0ull;
+    return;
+  }
+  if (tid == 0) s_tile = (int)atomicAdd(&tile_ctr[d], 1u);
+  for (int i = tid; i < kSortWaves * kSortRadix; i += kSortThreads) (&lds.wcnt[0][0])[i] = 0;
+  if (tid < kSortRadix) lds.thist[tid] = 0u;
+  __syncthreads();
+  const int tile = s_tile;
+  if (tid < ndig) lb_next[(size_t)tile * kSortRadix + tid] = 0ull;
+  if ((int64_t)(tile + 1) * kSortTile <= P)
+    sweep_tile<T, true>(lds, tile, d, x, y, N, P, keys0, keys1, idx0, idx1, ids_out, dig_off,
+                        pass, lb_cur, status);
+  else
+    sweep_last<T>(lds, tile, d, x, y, N, P, keys0, keys1, idx0, idx1, ids_out, dig_off, pass,
+                  lb_cur, status);
 }
 
 // Points given in ascending order: the sorted coordinates and identity ids as

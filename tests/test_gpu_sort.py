@@ -60,6 +60,9 @@ def cases(dtype):
                          np.array([-0.0, 0.0, -1.0] * 4000)),
         "all equal": (np.full(9000, 0.375), np.full(11000, 0.375)),
         "one point each": (np.array([0.5]), np.array([0.5])),
+        # radix tiles hold 8192 points: whole tiles only, and one point past them
+        "two whole tiles": (g.random(10000), g.random(6384)),
+        "one tile and a point": (g.random(4096), g.random(4097)),
     }
     if dtype == np.float64:
         e = g.integers(-300, 300, 30000).astype(np.float64)
