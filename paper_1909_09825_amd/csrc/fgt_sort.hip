@@ -36,7 +36,7 @@ constexpr int kRaw = 2;
 // A look-back wait longer than this means a predecessor tile never published;
 // the pass then stops waiting and raises kStatusInternal instead of hanging.
 constexpr uint32_t kSpinLimit = 1u << 24;
-constexpr int kLookWindow = 8;
+constexpr int kLookWindow = 4;   // predecessors read per look-back step
 
 __global__ void k_clear(uint32_t* __restrict__ p, size_t n_words) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -397,7 +397,8 @@ struct SweepLds {
 };
 
 // One tile of a radix pass.  kFull: the tile holds kSortTile points (every
-// tile but the last), so no item needs a bounds check.
+// tile but the last), so no item needs a bounds check.  The last tile's loads
+// read a clamped, in-bounds index and mask the value: no branch per item.
 template <class T, bool kFull>
 __device__ __forceinline__ void sweep_tile(
     SweepLds<T>& lds, int tile, int d, const T* __restrict__ x, const T* __restrict__ y,
@@ -441,9 +442,8 @@ __device__ __forceinline__ void sweep_tile(
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
       const int64_t p = base + i * kWave + lane;
-      z[i] = (!kFull && p >= P) ? T(0)
-           : p < N               ? __builtin_nontemporal_load(&y[p])
-                                 : __builtin_nontemporal_load(&x[p - N]);
+      const int64_t pc = (kFull || p < P) ? p : P - 1;   // in bounds; masked below
+      z[i] = pc < N ? __builtin_nontemporal_load(&y[pc]) : __builtin_nontemporal_load(&x[pc - N]);
       id[i] = (kFull || p < P) ? (uint32_t)p : 0u;
     }
     const Codec<T> cd = codec_of<T>(pass);
@@ -457,16 +457,22 @@ __device__ __forceinline__ void sweep_tile(
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
       const int64_t p = base + i * kWave + lane;
-      key[i] = (kFull || p < P) ? kin[p] : (K)0;
-      id[i] = (kFull || p < P) ? iin[p] : 0u;
+      const int64_t pc = (kFull || p < P) ? p : P - 1;
+      const K kv = kin[pc];
+      const uint32_t iv = iin[pc];
+      key[i] = (kFull || p < P) ? kv : (K)0;
+      id[i] = (kFull || p < P) ? iv : 0u;
     }
     asm volatile("" ::: "memory");
   } else {
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
       const int64_t p = base + i * kWave + lane;
-      key[i] = (kFull || p < P) ? __builtin_nontemporal_load(&kin[p]) : (K)0;
-      id[i] = (kFull || p < P) ? __builtin_nontemporal_load(&iin[p]) : 0u;
+      const int64_t pc = (kFull || p < P) ? p : P - 1;
+      const K kv = __builtin_nontemporal_load(&kin[pc]);
+      const uint32_t iv = __builtin_nontemporal_load(&iin[pc]);
+      key[i] = (kFull || p < P) ? kv : (K)0;
+      id[i] = (kFull || p < P) ? iv : 0u;
     }
   }
 
@@ -670,18 +676,6 @@ __device__ __forceinline__ void sweep_tile(
   }
 }
 
-// The last, partial tile: a call of its own, so that its bounds checks do not
-// raise the register pressure of the full tiles' code.
-template <class T>
-__device__ __noinline__ void sweep_last(
-    SweepLds<T>& lds, int tile, int d, const T* __restrict__ x, const T* __restrict__ y,
-    int64_t N, int64_t P, void* keys0, void* keys1, uint32_t* idx0, uint32_t* idx1,
-    uint32_t* __restrict__ ids_out, const uint32_t* __restrict__ dig_off,
-    const PassInfo* __restrict__ pass, uint64_t* lb_cur, uint32_t* __restrict__ status) {
-  sweep_tile<T, false>(lds, tile, d, x, y, N, P, keys0, keys1, idx0, idx1, ids_out, dig_off, pass,
-                       lb_cur, status);
-}
-
 template <class T>
 __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     int d, const T* __restrict__ x, const T* __restrict__ y, int64_t N,
@@ -714,8 +708,8 @@ __global__ __launch_bounds__(kSortThreads, 4) void k_onesweep(
     sweep_tile<T, true>(lds, tile, d, x, y, N, P, keys0, keys1, idx0, idx1, ids_out, dig_off,
                         pass, lb_cur, status);
   else
-    sweep_last<T>(lds, tile, d, x, y, N, P, keys0, keys1, idx0, idx1, ids_out, dig_off, pass,
-                  lb_cur, status);
+    sweep_tile<T, false>(lds, tile, d, x, y, N, P, keys0, keys1, idx0, idx1, ids_out, dig_off,
+                         pass, lb_cur, status);
 }
 
 // Points given in ascending order: the sorted coordinates and identity ids as
