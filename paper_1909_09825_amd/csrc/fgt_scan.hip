@@ -474,26 +474,50 @@ __device__ __forceinline__ void final_fast_body(const Modes& md, const T* dz, co
   }
 }
 
-// Two instantiations: moment counts up to kKSteps[2] (the usual case) and the
-// larger ones up to kFastMoments, so that the common kernel keeps fewer
-// registers (its moment arrays are shorter) and runs more waves per SIMD.
-template <class T, int NM, int KMAX>
-__global__ __launch_bounds__(256) void k_wfinal_fast(const void* keys0, const void* keys1,
-                                                     const PassInfo* __restrict__ pass,
-                                                     const T* __restrict__ bs,
-                                                     const uint32_t* __restrict__ ids, int64_t P,
-                                                     int64_t tiles, int vec, Modes md,
-                                                     const T* __restrict__ agg,
-                                                     const T* __restrict__ carry,
-                                                     const int32_t* __restrict__ tile_k,
-                                                     ScanOut<T> out) {
-  constexpr int KMIN = KMAX == kKSteps[2] ? 0 : kKSteps[2] + 1;
+// Tiles of the rare classes (more moments, or wide) are looked for by waves
+// that each test kRareSpan tiles spread over the whole sequence (tile
+// w + j * waves for lane j): when there are none, the kernel costs one load
+// per wave instead of one wave per tile, and where there are many (clustered
+// data) they are shared evenly between the waves.
+constexpr int kRareSpan = 4;
+
+__host__ __device__ __forceinline__ int64_t rare_waves(int64_t tiles) {
+  return (tiles + kRareSpan - 1) / kRareSpan;
+}
+
+// Calls body(tile, K) for every tile whose count K satisfies is_mine(K).
+template <class Pred, class Body>
+__device__ __forceinline__ void for_rare_tiles(const int32_t* __restrict__ tile_k, int64_t tiles,
+                                               Pred is_mine, Body body) {
   const int lane = threadIdx.x % kWave;
-  const int64_t tile = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
-  if (tile >= tiles) return;
-  const int K = tile_k[tile];
-  if (K < KMIN || K > KMAX) return;   // another kernel's tile
-  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
+  const int64_t nw = rare_waves(tiles);
+  const int64_t w = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+  if (w >= nw) return;
+  const int64_t t = w + (int64_t)lane * nw;
+  const bool in = lane < kRareSpan && t < tiles;
+  const int Kl = in ? tile_k[t] : 0;
+  uint64_t todo = __ballot(in && is_mine(Kl));
+#pragma unroll 1
+  while (todo) {
+    const int j = __builtin_ctzll(todo);
+    todo &= todo - 1;
+    // Tile and count as lane values (a shuffle): taken as wave-uniform, they
+    // led the compiler to a schedule with ~90 more registers per lane.
+    const int jv = __shfl(j, lane);
+    body(w + (int64_t)jv * nw, __shfl(Kl, jv));
+  }
+}
+
+// One tile of k_wfinal_fast.
+template <class T, int NM, int KMAX>
+__device__ __forceinline__ void wfinal_fast_tile(const KeyView<T>& keys,
+                                                 const T* __restrict__ bs,
+                                                 const uint32_t* __restrict__ ids, int64_t P,
+                                                 int vec, const Modes& md,
+                                                 const T* __restrict__ agg,
+                                                 const T* __restrict__ carry, ScanOut<T> out,
+                                                 int64_t tile, int K) {
+  const int lane = threadIdx.x % kWave;
   const int64_t t0 = tile * kWTile;
   const int64_t base = t0 + lane * kScanChunk;
   T zc[kScanChunk], bc[kScanChunk], dz[kScanChunk], sc[kScanChunk], acc[kScanChunk];
@@ -520,28 +544,49 @@ __global__ __launch_bounds__(256) void k_wfinal_fast(const void* keys0, const vo
   scatter_chunk(out, ic, acc);
 }
 
+// Two instantiations: moment counts up to kKSteps[2] (the usual case: one
+// wave per tile) and the larger ones up to kFastMoments (rare: see
+// for_rare_tiles), so that the common kernel keeps fewer registers (its
+// moment arrays are shorter) and runs more waves per SIMD.
+template <class T, int NM, int KMAX>
+__global__ __launch_bounds__(256) void k_wfinal_fast(const void* keys0, const void* keys1,
+                                                     const PassInfo* __restrict__ pass,
+                                                     const T* __restrict__ bs,
+                                                     const uint32_t* __restrict__ ids, int64_t P,
+                                                     int64_t tiles, int vec, Modes md,
+                                                     const T* __restrict__ agg,
+                                                     const T* __restrict__ carry,
+                                                     const int32_t* __restrict__ tile_k,
+                                                     ScanOut<T> out) {
+  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
+  if constexpr (KMAX == kKSteps[2]) {
+    const int64_t tile = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    if (tile >= tiles) return;
+    const int K = tile_k[tile];
+    if (K < 0 || K > KMAX) return;   // another kernel's tile
+    wfinal_fast_tile<T, NM, KMAX>(keys, bs, ids, P, vec, md, agg, carry, out, tile, K);
+  } else {
+    for_rare_tiles(tile_k, tiles, [](int K) { return K > kKSteps[2] && K <= KMAX; },
+                   [&](int64_t tile, int K) {
+                     wfinal_fast_tile<T, NM, KMAX>(keys, bs, ids, P, vec, md, agg, carry, out,
+                                                   tile, K);
+                   });
+  }
+}
+
 // ---------------------------------------------------------------------------
 // k_wfinal: the other tiles.  Per mode: the lanes' chunk maps, their inclusive
 // prefix (forward) and suffix (backward) over the wave, the tile carries, the
 // sweeps.
 // ---------------------------------------------------------------------------
+
+// One tile of k_wfinal.
 template <class T, int NM>
-__global__ __launch_bounds__(256) void k_wfinal(const void* keys0, const void* keys1,
-                                                const PassInfo* __restrict__ pass,
-                                                const T* __restrict__ bs,
-                                                const uint32_t* __restrict__ ids, int64_t P,
-                                                int64_t tiles, int vec, Modes md,
-                                                const T* __restrict__ carry,
-                                                const int32_t* __restrict__ tile_k,
-                                                ScanOut<T> out) {
+__device__ __forceinline__ void wfinal_tile(const KeyView<T>& keys, const T* __restrict__ bs,
+                                            const uint32_t* __restrict__ ids, int64_t P, int vec,
+                                            const Modes& md, const T* __restrict__ carry,
+                                            ScanOut<T> out, int64_t tile) {
   const int lane = threadIdx.x % kWave;
-  const int64_t tile = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
-  if (tile >= tiles) return;
-  {
-    const int K = tile_k[tile];
-    if (K >= 0 && K <= kFastMoments) return;   // k_wfinal_fast's tile
-  }
-  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
   const int64_t t0 = tile * kWTile;
   const int64_t base = t0 + lane * kScanChunk;
   T zc[kScanChunk], bc[kScanChunk], dz[kScanChunk], sc[kScanChunk], acc[kScanChunk];
@@ -584,6 +629,22 @@ __global__ __launch_bounds__(256) void k_wfinal(const void* keys0, const void* k
   scatter_chunk(out, ic, acc);
 }
 
+template <class T, int NM>
+__global__ __launch_bounds__(256) void k_wfinal(const void* keys0, const void* keys1,
+                                                const PassInfo* __restrict__ pass,
+                                                const T* __restrict__ bs,
+                                                const uint32_t* __restrict__ ids, int64_t P,
+                                                int64_t tiles, int vec, Modes md,
+                                                const T* __restrict__ carry,
+                                                const int32_t* __restrict__ tile_k,
+                                                ScanOut<T> out) {
+  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
+  // the tiles that k_wfinal_fast does not take
+  for_rare_tiles(tile_k, tiles, [](int K) { return K < 0 || K > kFastMoments; },
+                 [&](int64_t tile, int) { wfinal_tile<T, NM>(keys, bs, ids, P, vec, md, carry, out,
+                                                            tile); });
+}
+
 template <class T>
 __global__ void k_fill_zero(T* __restrict__ u, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -618,11 +679,13 @@ hipError_t scan_nm(const Workspace& w, const Modes& md, int64_t P, const T* b_in
   hipLaunchKernelGGL((k_wfinal_fast<T, NM, kKSteps[2]>), grid, dim3(256), 0, s, w.keys[0],
                      w.keys[1], w.pass, b, w.ids, P, tiles, vec, md, (const T*)w.agg,
                      (const T*)w.carry, w.tile_k, out);
-  hipLaunchKernelGGL((k_wfinal_fast<T, NM, kFastMoments>), grid, dim3(256), 0, s, w.keys[0],
+  // The rare classes: one wave per kRareSpan tiles.
+  const dim3 rare_grid((unsigned)((rare_waves(tiles) + 3) / 4));
+  hipLaunchKernelGGL((k_wfinal_fast<T, NM, kFastMoments>), rare_grid, dim3(256), 0, s, w.keys[0],
                      w.keys[1], w.pass, b, w.ids, P, tiles, vec, md, (const T*)w.agg,
                      (const T*)w.carry, w.tile_k, out);
-  hipLaunchKernelGGL((k_wfinal<T, NM>), grid, dim3(256), 0, s, w.keys[0], w.keys[1], w.pass, b,
-                     w.ids, P, tiles, vec, md, (const T*)w.carry, w.tile_k, out);
+  hipLaunchKernelGGL((k_wfinal<T, NM>), rare_grid, dim3(256), 0, s, w.keys[0], w.keys[1], w.pass,
+                     b, w.ids, P, tiles, vec, md, (const T*)w.carry, w.tile_k, out);
   tl->mark(s);
   return hipGetLastError();
 }
