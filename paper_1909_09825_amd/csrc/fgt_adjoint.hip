@@ -23,8 +23,9 @@
 //                     the strengths when the tile is short on the decay scale)
 //   carries           the three-level tile carries over 2 x modes scans
 //   k_adj_final_fast  tiles with at most kAdjMoments moments: chunk carries from
-//                     the moments, both channels' sweeps, scatter of the gradients
-//   k_adj_final       the other tiles: chunk and wave scans of both channels
+//                     the moments, both channels' sweeps, scatter of the gradients;
+//                     the other tiles (wide, or more moments) by chunk and wave
+//                     scans of both channels, in the same launch
 //   k_adj_delta       sum of the tiles' parts of dL/ddelta
 #include "fgt_device.h"
 
@@ -287,6 +288,153 @@ __device__ __forceinline__ void stage_tile(Staged2<T>& st, const KeyView<T>& key
 }
 
 // ---------------------------------------------------------------------------
+// Tiles outside the moment path (wide, or many moments): chunk and wave scans
+// of both channels.  Run by k_adj_final_fast's block for such a tile, in the
+// staging part of its LDS.
+// ---------------------------------------------------------------------------
+template <class T, int NM>
+__device__ __forceinline__ void adj_general_tile(
+    Staged2<T>& st, Seg<T> (&wtot)[2][kScanWaves][2], double* wsum, const KeyView<T>& keys,
+    const T* __restrict__ b, const T* __restrict__ bt, const uint32_t* __restrict__ ids,
+    int64_t P, const Modes& md, const T* __restrict__ carry, const AdjOut<T>& out, int64_t tile) {
+  constexpr int NQ = 2 * NM;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int64_t t0 = tile * kScanTile;
+  const int n = (int)((P - t0) < kScanTile ? (P - t0) : kScanTile);
+
+  stage_tile(st, keys, b, bt, ids, t0, P);
+  T zprev = t0 > 0 ? keys(t0 - 1) : T(0);
+  const double zc = 0.5 * ((double)keys(0) + (double)keys(P - 1));
+  __syncthreads();
+
+  const int e0 = tid * kScanChunk;
+  T dz[kScanChunk], bb[kScanChunk], bg[kScanChunk], za[kScanChunk];
+  uint32_t myid[kScanChunk];
+  T dzmax = T(0);
+  {
+    T zl = tid == 0 ? (t0 > 0 ? zprev : st.z[lds_pos(0)]) : st.z[lds_pos(e0 - 1)];
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) {
+      const int e = e0 + j;
+      const T zj = st.z[lds_pos(e)];
+      dz[j] = (e < n) ? zj - zl : T(0);
+      bb[j] = st.b[lds_pos(e)];
+      bg[j] = st.bt[lds_pos(e)];
+      za[j] = zj;
+      myid[j] = st.id[lds_pos(e)];
+      zl = (e < n) ? zj : zl;
+      dzmax = dz[j] > dzmax ? dz[j] : dzmax;
+    }
+  }
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) {
+    const T other = shfl_xor(dzmax, o);
+    dzmax = other > dzmax ? other : dzmax;
+  }
+
+  T dacc0[kScanChunk], acc1[kScanChunk], dacc1[kScanChunk];
+#pragma unroll
+  for (int j = 0; j < kScanChunk; ++j) {
+    dacc0[j] = T(0);
+    acc1[j] = T(0);
+    dacc1[j] = T(0);
+  }
+
+#pragma unroll 1
+  for (int k = 0; k < NM; ++k) {
+    const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
+    const T om_re = T(md.om_re[k]), om_im = T(md.om_im[k]);
+    const T dm_re = T(md.dom_re[k]), dm_im = T(md.dom_im[k]);
+    const double rr = md.tau_abs[k] * (double)dzmax;
+    int D = kTaylorMax;
+#pragma unroll
+    for (int d = kTaylorMax; d >= 1; --d)
+      if (rr <= md.taylor_thr[d]) D = d;
+    const T dz_lim = T(md.dz_lim[k]);
+    C<T> ex[kScanChunk];
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) ex[j] = {T(0), T(0)};
+#pragma unroll
+    for (int m = kTaylorMax; m >= 0; --m) {
+      if (m <= D) {
+        const T c_re = T(md.coef_re[k][m]), c_im = T(md.coef_im[k][m]);
+#pragma unroll
+        for (int j = 0; j < kScanChunk; ++j) {
+          ex[j].re = fma(ex[j].re, dz[j], c_re);
+          ex[j].im = fma(ex[j].im, dz[j], c_im);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j)
+      if (dz[j] > dz_lim) ex[j] = exp_neg_general<T>(tr, ti, dz[j]);
+
+    C<T> cf[2], cb[2];
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch) {
+      T w[kScanChunk];
+#pragma unroll
+      for (int j = 0; j < kScanChunk; ++j) w[j] = ch ? bg[j] : bb[j];
+      Seg<T> s;
+      s.a = ex[0];
+      s.f = {w[0], T(0)};
+#pragma unroll
+      for (int j = 1; j < kScanChunk; ++j) {
+        s.a = cmul(s.a, ex[j]);
+        s.f = cfma(ex[j], s.f, C<T>{w[j], T(0)});
+      }
+      s.g = {T(0), T(0)};
+#pragma unroll
+      for (int j = kScanChunk - 1; j >= 0; --j) s.g = cmul(ex[j], cadd(s.g, C<T>{w[j], T(0)}));
+      Seg<T> pf, sb;
+      wave_scans(s, lane, pf, sb);
+      if (lane == kWave - 1) wtot[ch][wave][0] = pf;
+      if (lane == 0) wtot[ch][wave][1] = sb;
+      __syncthreads();
+      const T* cr = carry + ((size_t)tile * NQ + ch * NM + k) * 4;
+      C<T> f = {cr[0], cr[1]};
+      C<T> g = {cr[2], cr[3]};
+      for (int ww = 0; ww < wave; ++ww) f = cfma(wtot[ch][ww][0].a, f, wtot[ch][ww][0].f);
+      for (int ww = kScanWaves - 1; ww > wave; --ww) g = cfma(wtot[ch][ww][1].a, g, wtot[ch][ww][1].g);
+      Seg<T> xl, xr;
+      xl.a.re = shfl_up(pf.a.re, 1); xl.a.im = shfl_up(pf.a.im, 1);
+      xl.f.re = shfl_up(pf.f.re, 1); xl.f.im = shfl_up(pf.f.im, 1);
+      xr.a.re = shfl_down(sb.a.re, 1); xr.a.im = shfl_down(sb.a.im, 1);
+      xr.g.re = shfl_down(sb.g.re, 1); xr.g.im = shfl_down(sb.g.im, 1);
+      if (lane > 0) f = cfma(xl.a, f, xl.f);
+      if (lane < kWave - 1) g = cfma(xr.a, g, xr.g);
+      cf[ch] = f;
+      cb[ch] = g;
+      __syncthreads();   // wtot of this channel is read before it is rewritten
+    }
+
+    C<T> h0 = cf[0], h1 = cf[1];
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) {
+      h0 = cfma(ex[j], h0, C<T>{bb[j], T(0)});
+      h1 = cfma(ex[j], h1, C<T>{bg[j], T(0)});
+      dacc0[j] = fma(dm_re, h0.re, fma(-dm_im, h0.im, dacc0[j]));
+      acc1[j] = fma(om_re, h1.re, fma(-om_im, h1.im, acc1[j]));
+      dacc1[j] = fma(dm_re, h1.re, fma(-dm_im, h1.im, dacc1[j]));
+    }
+    C<T> g0 = cb[0], g1 = cb[1];
+#pragma unroll
+    for (int j = kScanChunk - 1; j >= 0; --j) {
+      dacc0[j] = fma(-dm_re, g0.re, fma(dm_im, g0.im, dacc0[j]));
+      acc1[j] = fma(om_re, g1.re, fma(-om_im, g1.im, acc1[j]));
+      dacc1[j] = fma(-dm_re, g1.re, fma(dm_im, g1.im, dacc1[j]));
+      g0 = cmul(ex[j], cadd(g0, C<T>{bb[j], T(0)}));
+      g1 = cmul(ex[j], cadd(g1, C<T>{bg[j], T(0)}));
+    }
+  }
+
+  const double part = adj_scatter(out, myid, bb, bg, za, dacc0, acc1, dacc1, zc);
+  if (out.part) block_part<T>(part, out.part + tile, wsum);
+}
+
+// ---------------------------------------------------------------------------
 // k_adj_final_fast
 // ---------------------------------------------------------------------------
 template <class T, int NM>
@@ -298,11 +446,15 @@ __global__ __launch_bounds__(kScanThreads) void k_adj_final_fast(
   constexpr int NQ = 2 * NM;
   const int64_t tile = blockIdx.x;
   const int K = tile_k[tile];
-  if (K < 0 || K > kAdjMoments) return;
   const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
   __shared__ AdjFastLds<T> lds;
   __shared__ T mtot[2][kAdjMoments + 1][kScanWaves];
   __shared__ double wsum[kScanWaves];
+  if (K < 0 || K > kAdjMoments) {
+    __shared__ Seg<T> wtot[2][kScanWaves][2];   // per channel and wave: forward, backward totals
+    adj_general_tile<T, NM>(lds.st, wtot, wsum, keys, b, bt, ids, P, md, carry, out, tile);
+    return;
+  }
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const int lane = tid % kWave;
@@ -486,167 +638,20 @@ __global__ __launch_bounds__(kScanThreads) void k_adj_final_fast(
   if (out.part) block_part<T>(part, out.part + tile, wsum);
 }
 
-// ---------------------------------------------------------------------------
-// k_adj_final: tiles outside the fast path (wide, or many moments).
-// ---------------------------------------------------------------------------
-template <class T, int NM>
-__global__ __launch_bounds__(kScanThreads) void k_adj_final(
-    const void* keys0, const void* keys1, const PassInfo* __restrict__ pass,
-    const T* __restrict__ b, const T* __restrict__ bt, const uint32_t* __restrict__ ids,
-    int64_t P, Modes md, const T* __restrict__ carry, const int32_t* __restrict__ tile_k,
-    AdjOut<T> out) {
-  constexpr int NQ = 2 * NM;
-  {
-    const int K = tile_k[blockIdx.x];
-    if (K >= 0 && K <= kAdjMoments) return;
-  }
-  const KeyView<T> keys = key_view<T>(keys0, keys1, pass);
-  __shared__ Staged2<T> st;
-  __shared__ Seg<T> wtot[2][kScanWaves][2];   // per channel and wave: forward, backward totals
-  __shared__ double wsum[kScanWaves];
-  const int tid = threadIdx.x;
-  const int wave = tid / kWave;
-  const int lane = tid % kWave;
-  const int64_t tile = blockIdx.x;
-  const int64_t t0 = tile * kScanTile;
-  const int n = (int)((P - t0) < kScanTile ? (P - t0) : kScanTile);
-
-  stage_tile(st, keys, b, bt, ids, t0, P);
-  T zprev = t0 > 0 ? keys(t0 - 1) : T(0);
-  const double zc = 0.5 * ((double)keys(0) + (double)keys(P - 1));
-  __syncthreads();
-
-  const int e0 = tid * kScanChunk;
-  T dz[kScanChunk], bb[kScanChunk], bg[kScanChunk], za[kScanChunk];
-  uint32_t myid[kScanChunk];
-  T dzmax = T(0);
-  {
-    T zl = tid == 0 ? (t0 > 0 ? zprev : st.z[lds_pos(0)]) : st.z[lds_pos(e0 - 1)];
-#pragma unroll
-    for (int j = 0; j < kScanChunk; ++j) {
-      const int e = e0 + j;
-      const T zj = st.z[lds_pos(e)];
-      dz[j] = (e < n) ? zj - zl : T(0);
-      bb[j] = st.b[lds_pos(e)];
-      bg[j] = st.bt[lds_pos(e)];
-      za[j] = zj;
-      myid[j] = st.id[lds_pos(e)];
-      zl = (e < n) ? zj : zl;
-      dzmax = dz[j] > dzmax ? dz[j] : dzmax;
-    }
-  }
-#pragma unroll
-  for (int o = kWave / 2; o >= 1; o >>= 1) {
-    const T other = shfl_xor(dzmax, o);
-    dzmax = other > dzmax ? other : dzmax;
-  }
-
-  T dacc0[kScanChunk], acc1[kScanChunk], dacc1[kScanChunk];
-#pragma unroll
-  for (int j = 0; j < kScanChunk; ++j) {
-    dacc0[j] = T(0);
-    acc1[j] = T(0);
-    dacc1[j] = T(0);
-  }
-
-#pragma unroll 1
-  for (int k = 0; k < NM; ++k) {
-    const T tr = T(md.tau_re[k]), ti = T(md.tau_im[k]);
-    const T om_re = T(md.om_re[k]), om_im = T(md.om_im[k]);
-    const T dm_re = T(md.dom_re[k]), dm_im = T(md.dom_im[k]);
-    const double rr = md.tau_abs[k] * (double)dzmax;
-    int D = kTaylorMax;
-#pragma unroll
-    for (int d = kTaylorMax; d >= 1; --d)
-      if (rr <= md.taylor_thr[d]) D = d;
-    const T dz_lim = T(md.dz_lim[k]);
-    C<T> ex[kScanChunk];
-#pragma unroll
-    for (int j = 0; j < kScanChunk; ++j) ex[j] = {T(0), T(0)};
-#pragma unroll
-    for (int m = kTaylorMax; m >= 0; --m) {
-      if (m <= D) {
-        const T c_re = T(md.coef_re[k][m]), c_im = T(md.coef_im[k][m]);
-#pragma unroll
-        for (int j = 0; j < kScanChunk; ++j) {
-          ex[j].re = fma(ex[j].re, dz[j], c_re);
-          ex[j].im = fma(ex[j].im, dz[j], c_im);
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < kScanChunk; ++j)
-      if (dz[j] > dz_lim) ex[j] = exp_neg_general<T>(tr, ti, dz[j]);
-
-    C<T> cf[2], cb[2];
-#pragma unroll
-    for (int ch = 0; ch < 2; ++ch) {
-      T w[kScanChunk];
-#pragma unroll
-      for (int j = 0; j < kScanChunk; ++j) w[j] = ch ? bg[j] : bb[j];
-      Seg<T> s;
-      s.a = ex[0];
-      s.f = {w[0], T(0)};
-#pragma unroll
-      for (int j = 1; j < kScanChunk; ++j) {
-        s.a = cmul(s.a, ex[j]);
-        s.f = cfma(ex[j], s.f, C<T>{w[j], T(0)});
-      }
-      s.g = {T(0), T(0)};
-#pragma unroll
-      for (int j = kScanChunk - 1; j >= 0; --j) s.g = cmul(ex[j], cadd(s.g, C<T>{w[j], T(0)}));
-      Seg<T> pf, sb;
-      wave_scans(s, lane, pf, sb);
-      if (lane == kWave - 1) wtot[ch][wave][0] = pf;
-      if (lane == 0) wtot[ch][wave][1] = sb;
-      __syncthreads();
-      const T* cr = carry + ((size_t)tile * NQ + ch * NM + k) * 4;
-      C<T> f = {cr[0], cr[1]};
-      C<T> g = {cr[2], cr[3]};
-      for (int ww = 0; ww < wave; ++ww) f = cfma(wtot[ch][ww][0].a, f, wtot[ch][ww][0].f);
-      for (int ww = kScanWaves - 1; ww > wave; --ww) g = cfma(wtot[ch][ww][1].a, g, wtot[ch][ww][1].g);
-      Seg<T> xl, xr;
-      xl.a.re = shfl_up(pf.a.re, 1); xl.a.im = shfl_up(pf.a.im, 1);
-      xl.f.re = shfl_up(pf.f.re, 1); xl.f.im = shfl_up(pf.f.im, 1);
-      xr.a.re = shfl_down(sb.a.re, 1); xr.a.im = shfl_down(sb.a.im, 1);
-      xr.g.re = shfl_down(sb.g.re, 1); xr.g.im = shfl_down(sb.g.im, 1);
-      if (lane > 0) f = cfma(xl.a, f, xl.f);
-      if (lane < kWave - 1) g = cfma(xr.a, g, xr.g);
-      cf[ch] = f;
-      cb[ch] = g;
-      __syncthreads();   // wtot of this channel is read before it is rewritten
-    }
-
-    C<T> h0 = cf[0], h1 = cf[1];
-#pragma unroll
-    for (int j = 0; j < kScanChunk; ++j) {
-      h0 = cfma(ex[j], h0, C<T>{bb[j], T(0)});
-      h1 = cfma(ex[j], h1, C<T>{bg[j], T(0)});
-      dacc0[j] = fma(dm_re, h0.re, fma(-dm_im, h0.im, dacc0[j]));
-      acc1[j] = fma(om_re, h1.re, fma(-om_im, h1.im, acc1[j]));
-      dacc1[j] = fma(dm_re, h1.re, fma(-dm_im, h1.im, dacc1[j]));
-    }
-    C<T> g0 = cb[0], g1 = cb[1];
-#pragma unroll
-    for (int j = kScanChunk - 1; j >= 0; --j) {
-      dacc0[j] = fma(-dm_re, g0.re, fma(dm_im, g0.im, dacc0[j]));
-      acc1[j] = fma(om_re, g1.re, fma(-om_im, g1.im, acc1[j]));
-      dacc1[j] = fma(-dm_re, g1.re, fma(dm_im, g1.im, dacc1[j]));
-      g0 = cmul(ex[j], cadd(g0, C<T>{bb[j], T(0)}));
-      g1 = cmul(ex[j], cadd(g1, C<T>{bg[j], T(0)}));
-    }
-  }
-
-  const double part = adj_scatter(out, myid, bb, bg, za, dacc0, acc1, dacc1, zc);
-  if (out.part) block_part<T>(part, out.part + tile, wsum);
-}
-
 template <class T>
 __global__ __launch_bounds__(256) void k_adj_delta(const double* __restrict__ part, int64_t n,
                                                    double scale, T* __restrict__ out) {
   __shared__ double wsum[4];
-  double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) acc += part[i];
+  // Eight partial sums a thread, so that eight loads are in flight (a fixed
+  // order: the result is the same on every run).
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t i = threadIdx.x;
+  for (; i + 7 * 256 < n; i += 8 * 256) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] += part[i + q * 256];
+  }
+  for (; i < n; i += 256) a[0] += part[i];
+  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   for (int o = kWave / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
   if (threadIdx.x % kWave == 0) wsum[threadIdx.x / kWave] = acc;
   __syncthreads();
@@ -669,9 +674,6 @@ hipError_t adjoint_nm(const Workspace& w, const Modes& md, int64_t M, int64_t N,
   hipLaunchKernelGGL((k_adj_final_fast<T, NM>), grid, dim3(kScanThreads), 0, s, w.keys[0],
                      w.keys[1], w.pass, (const T*)w.b, (const T*)w.bt, (const uint32_t*)w.ids, P,
                      md, (const T*)w.agg, (const T*)w.carry, w.tile_k, out);
-  hipLaunchKernelGGL((k_adj_final<T, NM>), grid, dim3(kScanThreads), 0, s, w.keys[0], w.keys[1],
-                     w.pass, (const T*)w.b, (const T*)w.bt, (const uint32_t*)w.ids, P, md,
-                     (const T*)w.carry, w.tile_k, out);
   if (ddelta)
     hipLaunchKernelGGL(k_adj_delta<T>, dim3(1), dim3(256), 0, s, (const double*)w.tile_part,
                        w.scan_tiles, -0.5 / delta, ddelta);
