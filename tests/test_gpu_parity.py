@@ -181,6 +181,25 @@ def test_nonfinite_is_reported():
     assert st == fgt.FGT_ENONFINITE
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_nonfinite_is_reported_multi_kernel(dtype):
+    """Above 4096 points fgt_eval runs the range, histogram and radix kernels;
+    a NaN or an infinity among the coordinates is reported there too, and a
+    finite call after it reads OK."""
+    g = np.random.default_rng(6)
+    x, y = g.random(5000), g.random(6000)
+    x[1234] = np.nan
+    _, _, st = gpu_eval(x, y, np.ones(6000), 1e-3, 6, dtype=dtype, case="nan, multi-kernel")
+    assert st == fgt.FGT_ENONFINITE
+    x[1234] = 0.5
+    y[77] = -np.inf
+    _, _, st = gpu_eval(x, y, np.ones(6000), 1e-3, 6, dtype=dtype, case="-inf, multi-kernel")
+    assert st == fgt.FGT_ENONFINITE
+    y[77] = 0.25
+    _, _, st = gpu_eval(x, y, np.ones(6000), 1e-3, 6, dtype=dtype, case="finite, multi-kernel")
+    assert st == fgt.FGT_OK
+
+
 @pytest.mark.parametrize("digits", [3, 4, 6])
 def test_fp32(digits):
     """FP32 inputs (the FP32-rounded values, cast exactly to FP64 for the oracle).
