@@ -108,8 +108,9 @@ size_t fgt_workspace_size(fgt_plan_t plan, int64_t M, int64_t N);
  *                once.
  *   u            may not alias x, y, alpha or ws.
  * M == 0 enqueues nothing; N == 0 writes zeros.  Problems with M + N <= 4096
- * run as one workgroup in one launch (the sort then orders every key bit);
- * larger ones as the sequence of sort and scan kernels.  Either way the
+ * run in two launches, one workgroup per mode and a sum over the modes (the
+ * sort then orders every key bit); larger ones as the sequence of sort and
+ * scan kernels.  Either way the
  * workspace afterwards holds the sorted state fgt_eval_sorted and fgt_backward
  * (FGT_SORTED) start from.
  * Non-finite coordinates are detected on the device and reported by

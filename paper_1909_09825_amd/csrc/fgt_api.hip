@@ -88,6 +88,7 @@ Workspace layout(void* base, int64_t P, int esz, int n_modes) {
   w.bt = (void*)w.idx[0];
   w.b = take((size_t)esz * (size_t)P);
   w.ids = (uint32_t*)take(sizeof(uint32_t) * (size_t)P);
+  w.small_part = P <= kSmallMax ? take((size_t)esz * nm * (size_t)P) : nullptr;
   w.total = off;
   return w;
 }

@@ -299,10 +299,14 @@ struct Workspace {
   void* carry;           // [tiles][scans][4] scalars: CF, CB (complex)
   void* chunk_agg;       // [chunks][modes][6]: composed (A, F, G) of 64 consecutive tiles
   void* chunk_carry;     // [chunks][modes][4]: CF, CB entering each chunk
+  void* small_part;      // [modes][P] per-mode sums of the one-launch path (P <= kSmallMax), else null
   size_t zero_bytes;     // bytes from `status` that the first kernel clears
   int64_t sort_tiles, scan_tiles, wave_tiles;   // radix tiles, adjoint scan tiles, forward scan tiles
   size_t total;
 };
+
+// Transforms with P = M + N up to this run as one block per mode (fgt_small.hip).
+constexpr int kSmallMax = 4096;
 
 // Phase boundaries for benchmark timing: mark() records the next event, if any.
 constexpr int kMaxPhases = 12;   // setup, 8 radix passes, tile reduce, carry, tile final

@@ -1,9 +1,11 @@
-// Small transforms in one workgroup (P = M + N <= kSmallMax): the whole of
-// fgt_eval -- the merged ascending sort of Section 4, the forward and backward
-// recurrences (4.5)-(4.6) of every mode and the sum Re(omega_k (h+ + h-)) at the
-// targets (4.1), (4.4) -- in a single launch, with the points held in LDS.  At
-// these sizes the multi-kernel path is bound by the latency of its ~20 launches
-// rather than by any one of them.
+// Small transforms (P = M + N <= kSmallMax): the whole of fgt_eval -- the
+// merged ascending sort of Section 4, the forward and backward recurrences
+// (4.5)-(4.6) of every mode and the sum Re(omega_k (h+ + h-)) at the targets
+// (4.1), (4.4) -- in two launches, with the points held in LDS: one workgroup
+// per mode, each sorting the points itself and writing its mode's sums, then
+// a sum over the modes in mode order (the same bits on every run) scattered to
+// the targets.  At these sizes the multi-kernel path is bound by the latency
+// of its ~20 launches rather than by any one of them.
 //
 //   keys   IEEE order keys of [y; x] (-0 read as +0) beside their merged indices;
 //   sort   a bitonic network over (key, index) pairs padded to a power of two:
@@ -13,15 +15,15 @@
 //          threads' chunk maps (A, F, G) are scanned over the wave and the
 //          waves' totals are composed in order, then each thread sweeps its
 //          chunk in both directions.
-// The sorted coordinates, merged ids and strengths are left in the workspace as
-// the multi-kernel path leaves them, so fgt_eval_sorted and fgt_backward with
-// FGT_SORTED start from them.  The sort here is exact (every key bit).
+// The sorted coordinates, merged ids and strengths are left in the workspace
+// (by the first workgroup) as the multi-kernel path leaves them, so
+// fgt_eval_sorted and fgt_backward with FGT_SORTED start from them.  The sort
+// here is exact (every key bit).
 #include "fgt_device.h"
 
 namespace fgt {
 namespace {
 
-constexpr int kSmallMax = 4096;
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallPer = kSmallMax / kSmallThreads;
 constexpr int kSmallWaves = kSmallThreads / kWave;
@@ -56,10 +58,11 @@ __device__ __forceinline__ void small_exps(const Modes& md, int k, const T* dz, 
     if (dz[j] > dz_lim) ex[j] = exp_neg_general<T>(T(md.tau_re[k]), T(md.tau_im[k]), dz[j]);
 }
 
-template <class T, int NM>
+// Block k: the sort, then mode k's sums at every sorted point into part[k][P].
+template <class T>
 __global__ __launch_bounds__(kSmallThreads) void k_small(
     const T* __restrict__ x, int64_t M, const T* __restrict__ y, const T* __restrict__ alpha,
-    int64_t N, Modes md, T* __restrict__ u, T* __restrict__ zs, uint32_t* __restrict__ ids,
+    int64_t N, Modes md, T* __restrict__ part, T* __restrict__ zs, uint32_t* __restrict__ ids,
     T* __restrict__ bs, PassInfo* __restrict__ pass, uint32_t* __restrict__ status) {
   using K = typename KeyOf<T>::type;
   __shared__ K skey[kSmallMax];
@@ -118,8 +121,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(
   }
   __syncthreads();
 
-  // The thread's points: coordinates, gaps, strengths; the sorted state is
-  // written to the workspace.
+  // The thread's points: coordinates, gaps, strengths; the first block writes
+  // the sorted state to the workspace.
+  const bool first = blockIdx.x == 0;
   const int p0 = tid * kSmallPer;
   T dz[kSmallPer], bb[kSmallPer], acc[kSmallPer];
   uint32_t id[kSmallPer];
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(
     zl = valid ? z : zl;
     dzmax = dz[c] > dzmax ? dz[c] : dzmax;
     acc[c] = T(0);
-    if (valid) {
+    if (valid && first) {
       zs[p] = z;
       ids[p] = id[c];
       bs[p] = bb[c];
@@ -148,8 +152,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(
     dzmax = other > dzmax ? other : dzmax;
   }
 
-#pragma unroll 1
-  for (int k = 0; k < NM; ++k) {
+  {
+    const int k = blockIdx.x;
     C<T> ex[kSmallPer];
     small_exps(md, k, dz, dzmax, ex);
     // Chunk map: A = prod e, F = forward fold from 0, G = backward fold from 0.
@@ -194,51 +198,52 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(
       acc[c] = fma(om_re, g.re, fma(-om_im, g.im, acc[c]));
       g = cmul(ex[c], cadd(g, C<T>{bb[c], T(0)}));
     }
-    __syncthreads();   // wtot is rewritten by the next mode
   }
 
+  T* __restrict__ mine = part + (size_t)blockIdx.x * (size_t)P;
 #pragma unroll
-  for (int c = 0; c < kSmallPer; ++c) {
-    const uint32_t o = id[c] - (uint32_t)N;   // targets only (ids >= N); padding's id is past M
-    if (id[c] != kNoSlot && id[c] >= (uint32_t)N && o < (uint32_t)M) u[o] = acc[c];
-  }
-  if (tid == 0) {
+  for (int c = 0; c < kSmallPer; ++c)
+    if (p0 + c < P) mine[p0 + c] = acc[c];
+  if (first && tid == 0) {
     *status = s_bad ? kStatusNonFinite : 0u;
     pass->final_buf = 0;
     pass->last_pass = -1;
   }
 }
 
-template <class T, int NM>
-hipError_t small_nm(const Workspace& w, const Modes& md, const T* x, int64_t M, const T* y,
-                    const T* alpha, int64_t N, T* u, hipStream_t s, Timeline* tl) {
-  tl->mark(s);
-  hipLaunchKernelGGL((k_small<T, NM>), dim3(1), dim3(kSmallThreads), 0, s, x, M, y, alpha, N, md,
-                     u, (T*)w.keys[0], w.ids, (T*)w.b, w.pass, w.status);
-  tl->mark(s);
-  return hipGetLastError();
+// u at the targets: the modes' sums added in mode order.
+template <class T>
+__global__ __launch_bounds__(256) void k_small_sum(const uint32_t* __restrict__ ids,
+                                                   const T* __restrict__ part, int nm, int64_t P,
+                                                   int64_t N, T* __restrict__ u) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const uint32_t id = ids[p];
+  if (id < (uint32_t)N) return;   // a source
+  T acc = part[p];
+  for (int k = 1; k < nm; ++k) acc += part[(size_t)k * (size_t)P + p];
+  u[id - (uint32_t)N] = acc;
 }
 
 }  // namespace
 
-// fgt_eval for P = M + N <= kSmallMax in one launch, one phase on tl; *done
+// fgt_eval for P = M + N <= kSmallMax in two launches, one phase on tl; *done
 // is false (and nothing is enqueued or recorded) for larger problems.
 template <class T>
 hipError_t small_eval(const Workspace& w, const Modes& md, const T* x, int64_t M, const T* y,
                       const T* alpha, int64_t N, T* u, hipStream_t s, Timeline* tl, bool* done) {
   *done = false;
   if (M + N > kSmallMax || M <= 0 || N <= 0) return hipSuccess;
+  if (md.n < 1 || md.n > FGT_MAX_MODES || !w.small_part) return hipErrorInvalidValue;
   *done = true;
-  switch (md.n) {
-    case 1: return small_nm<T, 1>(w, md, x, M, y, alpha, N, u, s, tl);
-    case 2: return small_nm<T, 2>(w, md, x, M, y, alpha, N, u, s, tl);
-    case 3: return small_nm<T, 3>(w, md, x, M, y, alpha, N, u, s, tl);
-    case 4: return small_nm<T, 4>(w, md, x, M, y, alpha, N, u, s, tl);
-    case 5: return small_nm<T, 5>(w, md, x, M, y, alpha, N, u, s, tl);
-    case 6: return small_nm<T, 6>(w, md, x, M, y, alpha, N, u, s, tl);
-    case 7: return small_nm<T, 7>(w, md, x, M, y, alpha, N, u, s, tl);
-    default: *done = false; return hipErrorInvalidValue;
-  }
+  const int64_t P = M + N;
+  tl->mark(s);
+  hipLaunchKernelGGL(k_small<T>, dim3((unsigned)md.n), dim3(kSmallThreads), 0, s, x, M, y, alpha,
+                     N, md, (T*)w.small_part, (T*)w.keys[0], w.ids, (T*)w.b, w.pass, w.status);
+  hipLaunchKernelGGL(k_small_sum<T>, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s,
+                     (const uint32_t*)w.ids, (const T*)w.small_part, md.n, P, N, (T*)u);
+  tl->mark(s);
+  return hipGetLastError();
 }
 
 template hipError_t small_eval<double>(const Workspace&, const Modes&, const double*, int64_t,

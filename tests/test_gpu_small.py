@@ -1,7 +1,8 @@
-"""The one-workgroup path that fgt_eval takes for P = M + N <= 4096.
+"""The small-transform path that fgt_eval takes for P = M + N <= 4096.
 
-It sorts (bitonic, exact, stable in the merged order), scans and scatters in a
-single launch, and leaves the sorted state in the workspace.  Checked here:
+One workgroup per mode sorts (bitonic, exact, stable in the merged order) and
+scans; a second launch adds the modes and scatters; the first workgroup leaves
+the sorted state in the workspace.  Checked here:
   * O1 (direct sum) within 2 E_n sum|alpha| and O2 (the oracle's SOE recurrence)
     within the rounding tolerance, over shapes at and around the size limit and
     the power-of-two padding (P = 1, 2, 3, 2047, 2048, 4095, 4096, 4097), ties
